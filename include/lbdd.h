@@ -1,0 +1,152 @@
+/*
+ * lbdd.h -- C ABI of the MI355X (gfx950) ASRAL solver for Load Balanced Demand
+ * Distribution under overload penalties (arXiv 2304.06543).
+ *
+ * Problem (Section 2.1, "Problem Statement"): given k service centers S, n
+ * demand units D, an integer cost matrix CM(d,s), a capacity c_s and a
+ * penalty for every unit a center takes beyond its capacity, find a complete
+ * allotment (every unit to exactly one center) with a small value of the
+ * objective of Equation (1): the sum of CM over the allotment plus the total
+ * overload penalty.  The solver runs ASRAL (Algorithm 2): units are allotted
+ * one at a time in ascending order of their cheapest cost, each allotment is
+ * followed by Negative Cycle Refinement (Algorithm 1) and, when the receiving
+ * center was already full, by Negative Path Refinement (Appendix A).
+ *
+ * Conventions for every function:
+ *   - Return LBDD_OK (0) or a negative LBDD_E_* code; nothing aborts.  The
+ *     calling thread's last failure is described by lbdd_last_error().
+ *   - All integers are host-endian.  CM is int32, row-major [n][k]:
+ *     CM(d_i, s_j) = cm[i * k + j], with 0 <= CM < 2^30.
+ *   - Capacities are int32 >= 0; penalties are int32 in [1, 2^30): the penalty
+ *     is one constant per center, charged for every unit beyond capacity
+ *     (the paper's experiments, Section 5; Definition of the penalty function
+ *     in Section 2 allows a monotone function, of which this is a special case).
+ *   - The objective is int64.
+ *   - Work is enqueued on the instance's HIP stream (hipStream_t passed as
+ *     void*; NULL means the default stream).  Calls that return results
+ *     synchronise with that stream.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *
+ * Ties (the paper breaks them "arbitrarily"; this library fixes them):
+ *   - a unit's most suitable center is the smallest index among its cheapest;
+ *   - units are processed by (cheapest cost, unit index) ascending;
+ *   - the best transfer of a center pair is the smallest transfer cost, then
+ *     the earliest-processed unit;
+ *   - Bellman-Ford runs in synchronous rounds, labels change only on strict
+ *     improvement, and a label's predecessor is the smallest node index that
+ *     attains it; a refinement is applied only if its cost is < 0.
+ */
+#ifndef LBDD_H
+#define LBDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LBDD_OK = 0,
+    LBDD_E_INVAL = -1,    /* bad argument or input value out of range */
+    LBDD_E_NOMEM = -2,    /* device or host allocation failed */
+    LBDD_E_DEVICE = -3,   /* a HIP runtime call failed */
+    LBDD_E_STATE = -4,    /* call not valid in the handle's current state */
+    LBDD_E_INTERNAL = -5  /* an invariant failed (e.g. Bellman-Ford found a
+                             negative cycle that Lemmas 1-2 rule out) */
+};
+
+#define LBDD_MAX_K 2048                /* centers per instance */
+#define LBDD_MAX_N 0x7fffffffLL        /* units per instance */
+
+/* lbdd_create flags */
+#define LBDD_CM_DEVICE 0x1u   /* cm is a device pointer; it is read during
+                                 lbdd_create only and never freed */
+/* lbdd_assignment flags */
+#define LBDD_OUT_DEVICE 0x1u  /* out is a device pointer */
+
+typedef struct lbdd_instance lbdd_instance;
+
+/* Create an instance and run the setup step of Algorithm 2 (step 1): each
+ * unit's most suitable center and the MinDistance processing order.
+ *   k, n        numbers of centers and units (1 <= k <= LBDD_MAX_K,
+ *               1 <= n <= LBDD_MAX_N)
+ *   cm          [n][k] int32 cost matrix, host memory unless LBDD_CM_DEVICE
+ *   capacity    [k] int32 host array, copied
+ *   penalty     [k] int32 host array, copied
+ *   hip_stream  stream all of this instance's work is enqueued on
+ *   out         receives the handle (owned by the caller; lbdd_destroy frees)
+ * The library keeps its own device copy of CM, rows permuted into processing
+ * order; the caller's buffer may be reused once this call returns.
+ * Errors: LBDD_E_INVAL (ranges above, NULL pointers, any CM entry outside
+ * [0, 2^30) -- checked on the device, so this call synchronises),
+ * LBDD_E_NOMEM, LBDD_E_DEVICE. */
+int lbdd_create(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity,
+                const int32_t *penalty, uint32_t flags, void *hip_stream,
+                lbdd_instance **out);
+
+/* Run all remaining iterations of Algorithm 2 (allot, Algorithm 1, and
+ * Appendix A when the receiving center was full).  Asynchronous: enqueued on
+ * the instance's stream.  Calling it on a solved instance does nothing.
+ * Errors: LBDD_E_INVAL (NULL), LBDD_E_DEVICE (launch failure). */
+int lbdd_solve(lbdd_instance *h);
+
+/* Run at most `iters` more iterations (iters >= 0).  Same semantics as
+ * lbdd_solve otherwise; used to inspect intermediate allotments. */
+int lbdd_solve_iters(lbdd_instance *h, int64_t iters);
+
+/* Objective Delta of Equation (1) for the current allotment (complete after
+ * lbdd_solve).  Synchronises.  Errors: LBDD_E_INVAL (NULL), LBDD_E_INTERNAL
+ * (the solve hit a failed invariant), LBDD_E_DEVICE. */
+int lbdd_objective(lbdd_instance *h, int64_t *out);
+
+/* Current allotment, one int32 center index per unit in the caller's unit
+ * order (-1 for units not yet allotted).  out holds n entries, host memory
+ * unless LBDD_OUT_DEVICE.  Synchronises.  Errors as lbdd_objective. */
+int lbdd_assignment(lbdd_instance *h, int32_t *out, uint32_t flags);
+
+/* Number of iterations done so far (0..n).  Synchronises. */
+int lbdd_progress(lbdd_instance *h, int64_t *iters_done);
+
+/* State snapshot for inspection, all host memory: load [k] int32 (units per
+ * center), W [k][k] uint64 best-transfer keys of the allotment-subspace graph
+ * (Definition of Gamma, Section 3.2; key = ((delta + 2^31) << 32) | rank,
+ * all ones = no transfer), order [n] int64 (unit index at each processing
+ * position).  Any pointer may be NULL.  Synchronises. */
+int lbdd_snapshot(lbdd_instance *h, int32_t *load, uint64_t *W, int64_t *order);
+
+/* Counters (int64, up to `count` of them, host memory):
+ *   [0] cycles applied  [1] paths applied  [2] units moved
+ *   [3] cycle searches run  [4] path searches run  [5] Bellman-Ford rounds
+ *   [6] rows rescanned  [7] iterations done  [8] cycle searches skipped
+ *       because the allotment left the anchor's transfer costs unchanged
+ * Synchronises.  Returns the number of counters written (>= 0). */
+int lbdd_stats(lbdd_instance *h, int64_t *out, int32_t count);
+
+/* Free the instance and all its device memory (synchronises its stream). */
+void lbdd_destroy(lbdd_instance *h);
+
+/* Description of the calling thread's last failure ("" if none). */
+const char *lbdd_last_error(void);
+
+/* Best-transfer table of an arbitrary allotment, scanning the whole cost
+ * matrix (the condensed allotment-subspace graph, Definition of Gamma in
+ * Section 3.2, with the cheapest edge per ordered pair as in the NCyc
+ * definition, Section 3.3): for u != v,
+ *   W[u][v] = min over units d with assign[d] == u of
+ *             ((CM(d,v) - CM(d,u) + 2^31) << 32) | rank[d]
+ * and all ones where no unit is allotted to u, and on the diagonal.
+ *   cm      [n][k] int32, device      assign [n] int32 in [-1, k), device
+ *   rank    [n] int32 >= 0 distinct, device (tie order of units)
+ *   W       [k][k] uint64, device, written
+ *   work    device scratch of at least lbdd_best_transfers_work_bytes(k, n)
+ * Asynchronous on `hip_stream`.  Errors: LBDD_E_INVAL (sizes, NULL),
+ * LBDD_E_DEVICE. */
+size_t lbdd_best_transfers_work_bytes(int32_t k, int64_t n);
+int lbdd_best_transfers(int32_t k, int64_t n, const int32_t *cm, const int32_t *assign,
+                        const int32_t *rank, uint64_t *W, void *work, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBDD_H */

@@ -1,0 +1,265 @@
+// capi.hip -- the C ABI declared in include/lbdd.h.
+//
+// An instance owns its device state for its whole life: the cost matrix with
+// rows permuted into processing order, the allotment, per-center member lists
+// and loads, the best-transfer table W and a few int64 scalars (objective,
+// progress, status, counters).  Nothing crosses the host/device boundary
+// between lbdd_create and the calls that return results.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/lbdd.h"
+#include "lbdd_dev.hpp"
+
+struct lbdd_instance {
+  int32_t k = 0;
+  int64_t n = 0;
+  hipStream_t st = nullptr;
+  int64_t enqueued = 0;                 // iterations launched so far
+  int32_t *cm = nullptr, *smin = nullptr, *cap = nullptr, *pen = nullptr;
+  int32_t *assign = nullptr, *load = nullptr, *members = nullptr, *slot = nullptr;
+  int32_t *unperm = nullptr;            // [n] staging for lbdd_assignment
+  int64_t *order = nullptr, *scalars = nullptr;
+  uint64_t *W = nullptr;
+
+  lbdd::InstView view() const {
+    lbdd::InstView v;
+    v.k = k; v.n = n; v.cm = cm; v.smin = smin; v.cap = cap; v.pen = pen;
+    v.assign = assign; v.load = load; v.members = members; v.slot = slot; v.W = W;
+    v.scalars = scalars;
+    return v;
+  }
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  if (e == hipErrorOutOfMemory)
+    return fail(LBDD_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
+  return fail(LBDD_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+  do {                                               \
+    hipError_t _e = (expr);                          \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+template <class T>
+hipError_t dalloc(T **p, size_t count) {
+  return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T) + 1);
+}
+
+void release(lbdd_instance *h) {
+  if (!h) return;
+  if (h->st) (void)hipStreamSynchronize(h->st);
+  else (void)hipDeviceSynchronize();
+  void *ptrs[] = {h->cm, h->smin, h->cap, h->pen, h->assign, h->load, h->members,
+                  h->slot, h->unperm, h->order, h->scalars, h->W};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  delete h;
+}
+
+// Read the device scalars after the stream has drained.
+int read_scalars(lbdd_instance *h, int64_t *sc) {
+  HIP_TRY(hipStreamSynchronize(h->st), "hipStreamSynchronize");
+  HIP_TRY(hipMemcpy(sc, h->scalars, sizeof(int64_t) * lbdd::SC_COUNT, hipMemcpyDeviceToHost),
+          "copy scalars");
+  if (sc[lbdd::SC_STATUS] != 0)
+    return fail(LBDD_E_INTERNAL,
+                "solve stopped at iteration %lld: Bellman-Ford found a negative cycle that the "
+                "refinement invariants rule out (status %lld)",
+                (long long)sc[lbdd::SC_DONE], (long long)sc[lbdd::SC_STATUS]);
+  return LBDD_OK;
+}
+
+constexpr int64_t ITERS_PER_LAUNCH = 1 << 16;
+
+}  // namespace
+
+extern "C" {
+
+const char *lbdd_last_error(void) { return g_err.c_str(); }
+
+int lbdd_create(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity,
+                const int32_t *penalty, uint32_t flags, void *hip_stream, lbdd_instance **out) {
+  g_err.clear();
+  if (!out) return fail(LBDD_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (k < 1 || k > LBDD_MAX_K) return fail(LBDD_E_INVAL, "k=%d outside [1, %d]", k, LBDD_MAX_K);
+  if (n < 1 || n > LBDD_MAX_N) return fail(LBDD_E_INVAL, "n=%lld outside [1, 2^31-1]", (long long)n);
+  if (!cm || !capacity || !penalty) return fail(LBDD_E_INVAL, "NULL input array");
+  if (flags & ~LBDD_CM_DEVICE) return fail(LBDD_E_INVAL, "unknown flags 0x%x", flags);
+  for (int32_t s = 0; s < k; ++s) {
+    if (capacity[s] < 0) return fail(LBDD_E_INVAL, "capacity[%d]=%d < 0", s, capacity[s]);
+    if (penalty[s] < 1 || penalty[s] >= lbdd::CM_LIMIT)
+      return fail(LBDD_E_INVAL, "penalty[%d]=%d outside [1, 2^30)", s, penalty[s]);
+  }
+  lbdd_instance *h = new (std::nothrow) lbdd_instance;
+  if (!h) return fail(LBDD_E_NOMEM, "host allocation");
+  h->k = k; h->n = n; h->st = static_cast<hipStream_t>(hip_stream);
+  const size_t nk = (size_t)n * (size_t)k;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = dalloc(&h->cm, nk);
+  if (e == hipSuccess) e = dalloc(&h->smin, (size_t)n);
+  if (e == hipSuccess) e = dalloc(&h->cap, (size_t)k);
+  if (e == hipSuccess) e = dalloc(&h->pen, (size_t)k);
+  if (e == hipSuccess) e = dalloc(&h->assign, (size_t)n);
+  if (e == hipSuccess) e = dalloc(&h->load, (size_t)k);
+  if (e == hipSuccess) e = dalloc(&h->members, nk);
+  if (e == hipSuccess) e = dalloc(&h->slot, (size_t)n);
+  if (e == hipSuccess) e = dalloc(&h->unperm, (size_t)n);
+  if (e == hipSuccess) e = dalloc(&h->order, (size_t)n);
+  if (e == hipSuccess) e = dalloc(&h->scalars, (size_t)lbdd::SC_COUNT);
+  if (e == hipSuccess) e = dalloc(&h->W, (size_t)k * k);
+  if (e != hipSuccess) { release(h); return hip_fail(e, "device allocation"); }
+
+  // setup scratch: the unpermuted CM (host input only), sort keys, a flag
+  const int32_t *cm_dev = cm;
+  int32_t *cm_tmp = nullptr, *bad = nullptr;
+  void *work = nullptr;
+  int rc = LBDD_OK;
+  do {
+    if (!(flags & LBDD_CM_DEVICE)) {
+      if ((e = dalloc(&cm_tmp, nk)) != hipSuccess) { rc = hip_fail(e, "device allocation"); break; }
+      if ((e = hipMemcpyAsync(cm_tmp, cm, nk * 4, hipMemcpyHostToDevice, h->st)) != hipSuccess) {
+        rc = hip_fail(e, "copy CM to device"); break;
+      }
+      cm_dev = cm_tmp;
+    }
+    if ((e = hipMalloc(&work, lbdd::setup_work_bytes(k, n))) != hipSuccess) { rc = hip_fail(e, "device allocation"); break; }
+    if ((e = dalloc(&bad, 1)) != hipSuccess) { rc = hip_fail(e, "device allocation"); break; }
+    int32_t zero = 0;
+    if ((e = hipMemcpyAsync(bad, &zero, 4, hipMemcpyHostToDevice, h->st)) != hipSuccess) { rc = hip_fail(e, "init flag"); break; }
+    if ((e = hipMemcpyAsync(h->cap, capacity, (size_t)k * 4, hipMemcpyHostToDevice, h->st)) != hipSuccess ||
+        (e = hipMemcpyAsync(h->pen, penalty, (size_t)k * 4, hipMemcpyHostToDevice, h->st)) != hipSuccess) {
+      rc = hip_fail(e, "copy capacities/penalties"); break;
+    }
+    if ((e = lbdd::launch_setup(k, n, cm_dev, h->cm, h->smin, h->order, bad, work, h->st)) != hipSuccess) {
+      rc = hip_fail(e, "setup kernels"); break;
+    }
+    if ((e = lbdd::launch_init_state(h->view(), h->st)) != hipSuccess) { rc = hip_fail(e, "init kernel"); break; }
+    int32_t bad_h = 0;
+    if ((e = hipMemcpyAsync(&bad_h, bad, 4, hipMemcpyDeviceToHost, h->st)) != hipSuccess ||
+        (e = hipStreamSynchronize(h->st)) != hipSuccess) {
+      rc = hip_fail(e, "setup"); break;
+    }
+    if (bad_h) rc = fail(LBDD_E_INVAL, "cost matrix has an entry outside [0, 2^30)");
+  } while (0);
+  if (h->st) (void)hipStreamSynchronize(h->st);
+  if (cm_tmp) (void)hipFree(cm_tmp);
+  if (work) (void)hipFree(work);
+  if (bad) (void)hipFree(bad);
+  if (rc != LBDD_OK) { release(h); return rc; }
+  *out = h;
+  return LBDD_OK;
+}
+
+int lbdd_solve_iters(lbdd_instance *h, int64_t iters) {
+  if (!h) return fail(LBDD_E_INVAL, "NULL handle");
+  if (iters < 0) return fail(LBDD_E_INVAL, "iters < 0");
+  int64_t end = h->enqueued + iters;
+  if (end > h->n || end < h->enqueued) end = h->n;
+  const lbdd::InstView v = h->view();
+  for (int64_t r = h->enqueued; r < end; r += ITERS_PER_LAUNCH) {
+    const int64_t r1 = (end - r > ITERS_PER_LAUNCH) ? r + ITERS_PER_LAUNCH : end;
+    HIP_TRY(lbdd::launch_solve(v, r, r1, h->st), "solve kernel launch");
+    h->enqueued = r1;
+  }
+  return LBDD_OK;
+}
+
+int lbdd_solve(lbdd_instance *h) {
+  if (!h) return fail(LBDD_E_INVAL, "NULL handle");
+  return lbdd_solve_iters(h, h->n);
+}
+
+int lbdd_objective(lbdd_instance *h, int64_t *out) {
+  if (!h || !out) return fail(LBDD_E_INVAL, "NULL argument");
+  int64_t sc[lbdd::SC_COUNT];
+  int rc = read_scalars(h, sc);
+  if (rc) return rc;
+  *out = sc[lbdd::SC_OBJECTIVE];
+  return LBDD_OK;
+}
+
+int lbdd_progress(lbdd_instance *h, int64_t *iters_done) {
+  if (!h || !iters_done) return fail(LBDD_E_INVAL, "NULL argument");
+  int64_t sc[lbdd::SC_COUNT] = {};
+  int rc = read_scalars(h, sc);
+  *iters_done = sc[lbdd::SC_DONE];
+  return rc;
+}
+
+int lbdd_assignment(lbdd_instance *h, int32_t *out, uint32_t flags) {
+  if (!h || !out) return fail(LBDD_E_INVAL, "NULL argument");
+  if (flags & ~LBDD_OUT_DEVICE) return fail(LBDD_E_INVAL, "unknown flags 0x%x", flags);
+  int32_t *dst = (flags & LBDD_OUT_DEVICE) ? out : h->unperm;
+  HIP_TRY(lbdd::launch_unpermute(h->n, h->order, h->assign, dst, h->st), "unpermute kernel");
+  int64_t sc[lbdd::SC_COUNT];
+  int rc = read_scalars(h, sc);
+  if (rc) return rc;
+  if (!(flags & LBDD_OUT_DEVICE))
+    HIP_TRY(hipMemcpy(out, h->unperm, (size_t)h->n * 4, hipMemcpyDeviceToHost), "copy assignment");
+  return LBDD_OK;
+}
+
+int lbdd_snapshot(lbdd_instance *h, int32_t *load, uint64_t *W, int64_t *order) {
+  if (!h) return fail(LBDD_E_INVAL, "NULL handle");
+  int64_t sc[lbdd::SC_COUNT];
+  int rc = read_scalars(h, sc);
+  if (rc) return rc;
+  if (load) HIP_TRY(hipMemcpy(load, h->load, (size_t)h->k * 4, hipMemcpyDeviceToHost), "copy load");
+  if (W) HIP_TRY(hipMemcpy(W, h->W, (size_t)h->k * h->k * 8, hipMemcpyDeviceToHost), "copy W");
+  if (order) HIP_TRY(hipMemcpy(order, h->order, (size_t)h->n * 8, hipMemcpyDeviceToHost), "copy order");
+  return LBDD_OK;
+}
+
+int lbdd_stats(lbdd_instance *h, int64_t *out, int32_t count) {
+  if (!h || (!out && count > 0) || count < 0) return fail(LBDD_E_INVAL, "bad argument");
+  int64_t sc[lbdd::SC_COUNT];
+  HIP_TRY(hipStreamSynchronize(h->st), "hipStreamSynchronize");
+  HIP_TRY(hipMemcpy(sc, h->scalars, sizeof sc, hipMemcpyDeviceToHost), "copy scalars");
+  const int m = count < lbdd::SC_NSTATS ? count : lbdd::SC_NSTATS;
+  for (int i = 0; i < m; ++i) out[i] = sc[lbdd::SC_STAT0 + i];
+  return m;
+}
+
+void lbdd_destroy(lbdd_instance *h) { release(h); }
+
+size_t lbdd_best_transfers_work_bytes(int32_t k, int64_t n) {
+  if (k < 1 || n < 0) return 0;
+  return lbdd::scan_work_bytes(k, n);
+}
+
+int lbdd_best_transfers(int32_t k, int64_t n, const int32_t *cm, const int32_t *assign,
+                        const int32_t *rank, uint64_t *W, void *work, void *hip_stream) {
+  g_err.clear();
+  if (k < 1 || k > LBDD_MAX_K) return fail(LBDD_E_INVAL, "k=%d outside [1, %d]", k, LBDD_MAX_K);
+  if (n < 0 || n > LBDD_MAX_N) return fail(LBDD_E_INVAL, "n=%lld outside [0, 2^31-1]", (long long)n);
+  if (!W || !work || (n > 0 && (!cm || !assign || !rank))) return fail(LBDD_E_INVAL, "NULL argument");
+  HIP_TRY(lbdd::launch_full_scan(k, n, cm, assign, rank, W, work, static_cast<hipStream_t>(hip_stream)),
+          "scan kernels");
+  return LBDD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// lbdd_dev.hpp -- device-side types and helpers shared by the HIP kernels of
+// the MI355X ASRAL solver.  gfx950 only: wave64, 160 KB LDS per CU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbdd {
+
+constexpr uint64_t KEY_NONE = ~0ull;          // "no transfer" in the best-transfer table
+constexpr int64_t DIST_NONE = INT64_MAX;      // unreachable Bellman-Ford label
+constexpr int32_t CM_LIMIT = 1 << 30;         // costs and penalties lie in [0, 2^30)
+
+// Best-transfer key of moving the unit at processing rank `rank` between two
+// centers with transfer cost `delta` (Definition of Gamma, Section 3.2):
+// unsigned order = (delta, rank) lexicographic, so a plain integer min picks
+// the cheapest transfer and, among equal costs, the earliest-processed unit.
+__device__ __host__ inline uint64_t pack_key(int32_t delta, uint32_t rank) {
+  return (uint64_t)(uint32_t)(delta + (int32_t)0x80000000u) << 32 | rank;
+}
+__device__ __host__ inline int32_t key_delta(uint64_t key) {
+  return (int32_t)((uint32_t)(key >> 32) - 0x80000000u);
+}
+__device__ __host__ inline uint32_t key_rank(uint64_t key) { return (uint32_t)key; }
+
+// Bellman-Ford candidate packed with its predecessor node so that one unsigned
+// min gives the smallest label and, among equal labels, the smallest node.
+// Labels are sums of at most LBDD_MAX_K+1 edges of magnitude < 2^31.
+constexpr int64_t DIST_BIAS = 1ll << 46;
+__device__ inline uint64_t pack_cand(int64_t dist, int32_t node) {
+  return (uint64_t)(dist + DIST_BIAS) << 16 | (uint32_t)node;
+}
+__device__ inline int64_t cand_dist(uint64_t c) { return (int64_t)(c >> 16) - DIST_BIAS; }
+__device__ inline int32_t cand_node(uint64_t c) { return (int32_t)(c & 0xffffu); }
+
+// Device view of one instance.  Rows of `cm` are in processing order: row r is
+// the unit processed in iteration r, so a best-transfer key's rank is the row.
+struct InstView {
+  int32_t k;
+  int64_t n;
+  const int32_t *cm;       // [n][k] permuted cost matrix
+  const int32_t *smin;     // [n] most suitable center of row r
+  const int32_t *cap;      // [k]
+  const int32_t *pen;      // [k]
+  int32_t *assign;         // [n] center of row r, -1 before its iteration
+  int32_t *load;           // [k] units per center
+  int32_t *members;        // [k][n] rows allotted to each center (first load[u])
+  int32_t *slot;           // [n] index of row r in its center's member list
+  uint64_t *W;             // [k][k] best-transfer table
+  int64_t *scalars;        // [SC_COUNT] objective, progress, status, counters
+};
+
+// layout of InstView::scalars
+enum : int {
+  SC_OBJECTIVE = 0,
+  SC_DONE = 1,          // iterations completed
+  SC_STATUS = 2,        // 0 ok, else an LBDD_E_* code
+  SC_STAT0 = 3,         // first of the counters reported by lbdd_stats
+  SC_NSTATS = 9,
+  SC_COUNT = SC_STAT0 + SC_NSTATS
+};
+enum : int {
+  ST_CYCLES = 0, ST_PATHS, ST_MOVES, ST_CYC_SEARCH, ST_PATH_SEARCH, ST_BF_ROUNDS,
+  ST_ROWS_SCANNED, ST_ITERS, ST_CYC_SKIPPED
+};
+
+// ---- host launchers (return hipError_t) ----
+// setup.hip: most suitable center, processing order, row permutation
+size_t setup_work_bytes(int32_t k, int64_t n);
+hipError_t launch_setup(int32_t k, int64_t n, const int32_t *cm_in, int32_t *cm_perm,
+                        int32_t *smin_perm, int64_t *order, int32_t *bad_flag, void *work,
+                        hipStream_t st);
+// solve.hip: iterations [r_begin, r_end) of the main loop
+hipError_t launch_init_state(const InstView &I, hipStream_t st);
+hipError_t launch_solve(const InstView &I, int64_t r_begin, int64_t r_end, hipStream_t st);
+hipError_t launch_unpermute(int64_t n, const int64_t *order, const int32_t *assign, int32_t *out,
+                            hipStream_t st);
+// scan.hip: whole-matrix best-transfer table
+size_t scan_work_bytes(int32_t k, int64_t n);
+hipError_t launch_full_scan(int32_t k, int64_t n, const int32_t *cm, const int32_t *assign,
+                            const int32_t *rank, uint64_t *W, void *work, hipStream_t st);
+
+}  // namespace lbdd

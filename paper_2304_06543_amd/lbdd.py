@@ -1,0 +1,215 @@
+"""Python binding of liblbdd.so (argument marshalling only).
+
+Every step of the solve runs in the HIP library; this module only converts
+arguments.  torch is used for device memory and streams.  There is no CPU
+fallback: if the built library is missing, loading raises.
+
+    inst = Instance(cm, capacity, penalty)     # cm: torch int32 (cuda) or numpy
+    inst.solve()
+    inst.objective(), inst.assignment()
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbdd.so")
+
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_INTERNAL = 0, -1, -2, -3, -4, -5
+CM_DEVICE = 0x1
+OUT_DEVICE = 0x1
+MAX_K = 2048
+STATS = ("cycles", "paths", "moves", "cycle_searches", "path_searches", "bf_rounds",
+         "rows_scanned", "iterations", "cycle_searches_skipped")
+
+# every symbol include/lbdd.h declares
+EXPORTS = ("lbdd_create", "lbdd_solve", "lbdd_solve_iters", "lbdd_objective",
+           "lbdd_assignment", "lbdd_progress", "lbdd_snapshot", "lbdd_stats",
+           "lbdd_destroy", "lbdd_last_error", "lbdd_best_transfers_work_bytes",
+           "lbdd_best_transfers")
+
+_lib = None
+
+
+class LbddError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbdd error {code}: {msg}")
+        self.code = code
+
+
+def load(path: str = LIB_PATH):
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2304_06543_amd.build`")
+    lib = C.CDLL(path)
+    P, I32, I64, U32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32
+    sig = {
+        "lbdd_create": ([I32, I64, P, P, P, U32, P, C.POINTER(P)], C.c_int),
+        "lbdd_solve": ([P], C.c_int),
+        "lbdd_solve_iters": ([P, I64], C.c_int),
+        "lbdd_objective": ([P, C.POINTER(I64)], C.c_int),
+        "lbdd_assignment": ([P, P, U32], C.c_int),
+        "lbdd_progress": ([P, C.POINTER(I64)], C.c_int),
+        "lbdd_snapshot": ([P, P, P, P], C.c_int),
+        "lbdd_stats": ([P, P, I32], C.c_int),
+        "lbdd_destroy": ([P], None),
+        "lbdd_last_error": ([], C.c_char_p),
+        "lbdd_best_transfers_work_bytes": ([I32, I64], C.c_size_t),
+        "lbdd_best_transfers": ([I32, I64, P, P, P, P, P, P], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc < 0:
+        raise LbddError(rc, load().lbdd_last_error().decode())
+    return rc
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _host_i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a), dtype=np.int32)
+
+
+class Instance:
+    """One LBDD instance living on the GPU (lbdd_create ... lbdd_destroy)."""
+
+    def __init__(self, cm, capacity, penalty, stream=None):
+        lib = load()
+        self._lib = lib
+        self._h = C.c_void_p()
+        cap = _host_i32(capacity)
+        pen = _host_i32(penalty)
+        if hasattr(cm, "is_cuda") and cm.is_cuda:
+            import torch
+            if cm.dtype != torch.int32 or not cm.is_contiguous() or cm.dim() != 2:
+                raise ValueError("cm must be a contiguous 2-D int32 tensor")
+            n, k = cm.shape
+            ptr, flags, self._keep = C.c_void_p(cm.data_ptr()), CM_DEVICE, cm
+        else:
+            cmh = _host_i32(cm)
+            if cmh.ndim != 2:
+                raise ValueError("cm must be 2-D [n][k]")
+            n, k = cmh.shape
+            ptr, flags, self._keep = cmh.ctypes.data_as(C.c_void_p), 0, cmh
+        if cap.shape != (k,) or pen.shape != (k,):
+            raise ValueError("capacity and penalty need k entries")
+        self.k, self.n = int(k), int(n)
+        self._stream = _stream_ptr(stream)
+        _check(lib.lbdd_create(self.k, self.n, ptr, cap.ctypes.data_as(C.c_void_p),
+                               pen.ctypes.data_as(C.c_void_p), flags, self._stream,
+                               C.byref(self._h)))
+        self._keep = None
+
+    def solve(self):
+        _check(self._lib.lbdd_solve(self._h))
+        return self
+
+    def solve_iters(self, iters: int):
+        _check(self._lib.lbdd_solve_iters(self._h, int(iters)))
+        return self
+
+    def objective(self) -> int:
+        out = C.c_int64()
+        _check(self._lib.lbdd_objective(self._h, C.byref(out)))
+        return int(out.value)
+
+    def progress(self) -> int:
+        out = C.c_int64()
+        _check(self._lib.lbdd_progress(self._h, C.byref(out)))
+        return int(out.value)
+
+    def assignment(self, device: bool = False):
+        """int32 center per unit (-1 if not yet allotted): numpy, or a torch
+        cuda tensor with device=True."""
+        if device:
+            import torch
+            out = torch.empty(self.n, dtype=torch.int32, device="cuda")
+            _check(self._lib.lbdd_assignment(self._h, C.c_void_p(out.data_ptr()), OUT_DEVICE))
+            return out
+        out = np.empty(self.n, np.int32)
+        _check(self._lib.lbdd_assignment(self._h, out.ctypes.data_as(C.c_void_p), 0))
+        return out
+
+    def snapshot(self):
+        """(load[k], W[k][k] uint64 keys, order[n])."""
+        load_ = np.empty(self.k, np.int32)
+        W = np.empty((self.k, self.k), np.uint64)
+        order = np.empty(self.n, np.int64)
+        _check(self._lib.lbdd_snapshot(self._h, load_.ctypes.data_as(C.c_void_p),
+                                       W.ctypes.data_as(C.c_void_p),
+                                       order.ctypes.data_as(C.c_void_p)))
+        return load_, W, order
+
+    def stats(self) -> dict:
+        out = np.zeros(len(STATS), np.int64)
+        m = _check(self._lib.lbdd_stats(self._h, out.ctypes.data_as(C.c_void_p), len(STATS)))
+        return {name: int(out[i]) for i, name in enumerate(STATS[:m])}
+
+    def close(self):
+        if self._h:
+            self._lib.lbdd_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def solve(cm, capacity, penalty, stream=None):
+    """Solve one instance; returns (objective, assignment as numpy int32)."""
+    with Instance(cm, capacity, penalty, stream) as inst:
+        inst.solve()
+        return inst.objective(), inst.assignment()
+
+
+def best_transfers_work_bytes(k: int, n: int) -> int:
+    return int(load().lbdd_best_transfers_work_bytes(int(k), int(n)))
+
+
+def best_transfers(cm, assign, rank, W=None, work=None, stream=None):
+    """Best-transfer table of an allotment over the whole cost matrix.
+
+    cm [n][k] int32, assign [n] int32, rank [n] int32: torch cuda tensors.
+    Returns W as a torch int64 tensor [k][k] holding the uint64 key bits."""
+    import torch
+    n, k = cm.shape
+    for t in (cm, assign, rank):
+        if not (t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()):
+            raise ValueError("cm, assign and rank must be contiguous int32 cuda tensors")
+    if W is None:
+        W = torch.empty((k, k), dtype=torch.int64, device=cm.device)
+    if work is None:
+        work = torch.empty(best_transfers_work_bytes(k, n), dtype=torch.uint8, device=cm.device)
+    _check(load().lbdd_best_transfers(int(k), int(n), C.c_void_p(cm.data_ptr()),
+                                      C.c_void_p(assign.data_ptr()), C.c_void_p(rank.data_ptr()),
+                                      C.c_void_p(W.data_ptr()), C.c_void_p(work.data_ptr()),
+                                      _stream_ptr(stream)))
+    return W

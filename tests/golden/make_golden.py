@@ -1,0 +1,47 @@
+"""Write the stored oracle results used by the GPU parity tests.
+
+    python -m tests.golden.make_golden
+
+Calls only the CPU oracle (oracle/) and the input generators (lbdd_inputs).
+For each workload it records the input hash, the objective, a sha256 of the
+int32 allotment (one center per unit, little-endian) and the oracle's counters.
+"""
+import hashlib
+import json
+import os
+import time
+
+import numpy as np
+
+import lbdd_inputs as L
+import oracle
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_results.json")
+
+
+def assignment_hash(a: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<i4").tobytes()).hexdigest()
+
+
+def main():
+    res = {}
+    for name in ("C1", "C2"):
+        inst = L.make_config(name)
+        t = time.time()
+        r = oracle.solve(*inst.arrays())
+        dt = time.time() - t
+        res[name] = dict(
+            k=inst.k, n=inst.n, input_sha256=L.input_hash(inst), objective=r.objective,
+            assignment_sha256=assignment_hash(r.assign),
+            assignment_head=r.assign[:16].tolist(),
+            load=r.load.tolist() if inst.k <= 128 else None,
+            stats=dict(zip(["cycles", "paths", "moves", "cycle_searches", "path_searches",
+                            "bf_rounds", "heap_pushes", "iterations"], r.stats.tolist())),
+            oracle_seconds=round(dt, 2))
+        print(name, res[name]["objective"], dt, flush=True)
+    with open(OUT, "w") as f:
+        json.dump(res, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+"""GPU parity: the HIP path against the CPU oracle, bit-exact.
+
+Everything compared here is integer: the processing order, the allotment, the
+loads, the int64 objective and the uint64 best-transfer keys.  The tie rules
+of both sides are the same readings of the paper, so equality is exact.
+All calls go through the C ABI (paper_2304_06543_amd.lbdd is ctypes only).
+"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import lbdd_inputs as L
+import oracle
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "oracle_results.json")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    import paper_2304_06543_amd.lbdd as lb
+    lb.load()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return lb
+
+
+def gpu_solve(lb, inst, device_cm=True):
+    import torch
+    cm = torch.from_numpy(inst.cm).cuda() if device_cm else inst.cm
+    with lb.Instance(cm, inst.cap, inst.pen) as I:
+        I.solve()
+        return I.objective(), I.assignment(), I.stats()
+
+
+def small_cases():
+    out = []
+    caps = ["tight", "loose", "zero", 2, "tight"]
+    for s in range(60):
+        k = [1, 2, 3, 4, 5, 7, 8, 12, 16, 33][s % 10]
+        n = [1, 2, 9, 40, 130, 257, 400][s % 7]
+        out.append(L.random_small(k=k, n=n, seed=100 + s, cm_hi=[3, 50, 1000][s % 3],
+                                  cap=caps[s % 5], pen_hi=[5, 80, 600][s % 3]))
+    return out
+
+
+def test_processing_order_matches_oracle(lb):
+    import torch
+    for inst in [L.make_config("C1"), L.random_small(k=5, n=3000, seed=1, cm_hi=3)]:
+        say("order", inst.name)
+        _, _, order, _ = oracle.setup(inst.cm)
+        with lb.Instance(torch.from_numpy(inst.cm).cuda(), inst.cap, inst.pen) as I:
+            _, _, g_order = I.snapshot()
+        assert np.array_equal(g_order, order)
+
+
+@pytest.mark.parametrize("inst", small_cases(), ids=lambda i: i.name)
+def test_small_instances_bit_exact(lb, inst):
+    say("small", inst.name)
+    ref = oracle.solve(*inst.arrays())
+    obj, a, _ = gpu_solve(lb, inst)
+    assert obj == ref.objective
+    assert np.array_equal(a, ref.assign)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_checkpoints_state_bit_exact(lb, seed):
+    """Allotment, loads, objective and the whole best-transfer table after
+    several intermediate iteration counts."""
+    import torch
+    inst = L.random_small(k=[3, 6, 9, 17, 40, 70][seed], n=220, seed=500 + seed,
+                          cm_hi=[4, 60, 300][seed % 3], pen_hi=90)
+    say("checkpoints", inst.name)
+    with lb.Instance(torch.from_numpy(inst.cm).cuda(), inst.cap, inst.pen) as I:
+        done = 0
+        for r in (1, 2, 7, 30, 64, 150, 220):
+            I.solve_iters(r - done)
+            done = r
+            assert I.progress() == r
+            ref = oracle.solve(*inst.arrays(), max_iters=r, want_W=True)
+            load, W, _ = I.snapshot()
+            assert I.objective() == ref.objective, r
+            assert np.array_equal(I.assignment(), ref.assign), r
+            assert np.array_equal(load, ref.load), r
+            assert np.array_equal(W, ref.W), r
+
+
+@pytest.mark.parametrize("k", [130, 140, 300])
+def test_w_placement_boundaries_bit_exact(lb, k):
+    """W in LDS (k <= ~135) and in global memory give the same results."""
+    inst = L.random_small(k=k, n=700, seed=k, cm_hi=200, pen_hi=300)
+    say("k-boundary", inst.name)
+    ref = oracle.solve(*inst.arrays())
+    obj, a, _ = gpu_solve(lb, inst)
+    assert obj == ref.objective and np.array_equal(a, ref.assign)
+
+
+def test_more_centers_than_threads_bit_exact(lb):
+    inst = L.random_small(k=1100, n=260, seed=11, cm_hi=500, cap=0, pen_hi=400)
+    say("k>1024", inst.name)
+    ref = oracle.solve(*inst.arrays())
+    obj, a, _ = gpu_solve(lb, inst)
+    assert obj == ref.objective and np.array_equal(a, ref.assign)
+
+
+def test_host_and_device_inputs_agree(lb):
+    inst = L.make_config("C1")
+    a1 = gpu_solve(lb, inst, device_cm=True)
+    a2 = gpu_solve(lb, inst, device_cm=False)
+    assert a1[0] == a2[0] and np.array_equal(a1[1], a2[1])
+
+
+def test_config_c1_bit_exact(lb):
+    inst = L.make_config("C1")
+    ref = oracle.solve(*inst.arrays())
+    obj, a, st = gpu_solve(lb, inst)
+    say("C1", obj, st)
+    assert obj == ref.objective and np.array_equal(a, ref.assign)
+    assert obj == pins.eq1(*inst.arrays(), a)
+
+
+def _golden(name):
+    with open(GOLD) as f:
+        return json.load(f)[name]
+
+
+def test_config_c2_bit_exact_against_stored_oracle(lb):
+    g = _golden("C2")
+    inst = L.make_config("C2")
+    assert L.input_hash(inst) == g["input_sha256"], "generator produced different inputs"
+    obj, a, st = gpu_solve(lb, inst)
+    say("C2", obj, st)
+    assert obj == g["objective"]
+    assert hashlib.sha256(a.astype("<i4").tobytes()).hexdigest() == g["assignment_sha256"]
+    assert obj == pins.eq1(*inst.arrays(), a)
+
+
+def test_solve_is_deterministic(lb):
+    inst = L.random_small(k=24, n=5000, seed=3, cm_hi=40, pen_hi=200)
+    r1 = gpu_solve(lb, inst)
+    r2 = gpu_solve(lb, inst)
+    assert r1[0] == r2[0] and np.array_equal(r1[1], r2[1])
+
+
+def test_invalid_cost_rejected(lb):
+    import torch
+    cm = np.ones((50, 4), np.int32)
+    cm[17, 2] = -3
+    with pytest.raises(lb.LbddError) as e:
+        lb.Instance(torch.from_numpy(cm).cuda(), np.ones(4), np.ones(4))
+    assert e.value.code == lb.E_INVAL
+    cm[17, 2] = 1 << 30
+    with pytest.raises(lb.LbddError):
+        lb.Instance(cm, np.ones(4), np.ones(4))
+    with pytest.raises(lb.LbddError):
+        lb.Instance(np.ones((5, 3), np.int32), np.array([1, -1, 1]), np.ones(3))
+    with pytest.raises(lb.LbddError):
+        lb.Instance(np.ones((5, 3), np.int32), np.ones(3), np.array([1, 0, 1]))
+
+
+# ------------------------------------------------ whole-matrix scan (a3)
+def _scan_case(k, n, seed, unallotted=0.1):
+    rng = np.random.default_rng(seed)
+    inst = L.random_small(k=k, n=n, seed=seed, cm_hi=2000) if n * k <= 5_000_000 else None
+    return inst, rng
+
+
+@pytest.mark.parametrize("k,n", [(1, 10), (8, 2000), (37, 5000), (100, 100_000), (131, 20_000)])
+def test_full_scan_bit_exact(lb, k, n):
+    import torch
+    rng = np.random.default_rng(k * 7 + n)
+    cm = rng.integers(0, 2000, size=(n, k), dtype=np.int64).astype(np.int32)
+    assign = rng.integers(-1, k, size=n).astype(np.int32)
+    rank = rng.permutation(n).astype(np.int32)
+    say("scan", k, n)
+    ref = oracle.best_transfers(cm, assign, rank.astype(np.int64))
+    W = lb.best_transfers(torch.from_numpy(cm).cuda(), torch.from_numpy(assign).cuda(),
+                          torch.from_numpy(rank).cuda())
+    got = W.cpu().numpy().view(np.uint64)
+    assert np.array_equal(got, ref)
+
+
+def test_full_scan_c3_size_bit_exact(lb):
+    """The whole-matrix scan at the largest single-instance size (k=500,
+    n=1,000,000, 2 GB of costs), on the processing order of that workload and
+    its most-suitable-center allotment, against the oracle's definition."""
+    import torch
+    inst = L.make_config("C3")
+    say("scan C3")
+    smin, _, order, rank = oracle.setup(inst.cm)
+    ref = oracle.best_transfers(inst.cm, smin, rank)
+    W = lb.best_transfers(torch.from_numpy(inst.cm).cuda(), torch.from_numpy(smin).cuda(),
+                          torch.from_numpy(rank.astype(np.int32)).cuda())
+    assert np.array_equal(W.cpu().numpy().view(np.uint64), ref)
