@@ -15,8 +15,10 @@ constexpr int32_t CM_LIMIT = 1 << 30;         // costs and penalties lie in [0, 
 // centers with transfer cost `delta` (Definition of Gamma, Section 3.2):
 // unsigned order = (delta, rank) lexicographic, so a plain integer min picks
 // the cheapest transfer and, among equal costs, the earliest-processed unit.
+// (The bias is added in unsigned arithmetic: delta + 2^31 in int32 would
+// overflow for every negative delta.)
 __device__ __host__ inline uint64_t pack_key(int32_t delta, uint32_t rank) {
-  return (uint64_t)(uint32_t)(delta + (int32_t)0x80000000u) << 32 | rank;
+  return (uint64_t)((uint32_t)delta ^ 0x80000000u) << 32 | rank;
 }
 __device__ __host__ inline int32_t key_delta(uint64_t key) {
   return (int32_t)((uint32_t)(key >> 32) - 0x80000000u);
