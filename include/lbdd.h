@@ -120,6 +120,9 @@ int lbdd_snapshot(lbdd_instance *h, int32_t *load, uint64_t *W, int64_t *order);
  *   [3] cycle searches run  [4] path searches run  [5] Bellman-Ford rounds
  *   [6] rows rescanned  [7] iterations done  [8] cycle searches skipped
  *       because the allotment left the anchor's transfer costs unchanged
+ *   [9] .. [12] device timer ticks spent in: allotment, cycle refinement,
+ *       path refinement, rescans after applied refinements (part of [10],[11])
+ *   [13] device timer frequency in kHz
  * Synchronises.  Returns the number of counters written (>= 0). */
 int lbdd_stats(lbdd_instance *h, int64_t *out, int32_t count);
 

@@ -92,7 +92,7 @@ int read_scalars(lbdd_instance *h, int64_t *sc) {
   return LBDD_OK;
 }
 
-constexpr int64_t ITERS_PER_LAUNCH = 1 << 16;
+constexpr int64_t ITERS_PER_LAUNCH = 1 << 21;   // one launch covers every workload here
 
 }  // namespace
 
@@ -239,8 +239,14 @@ int lbdd_stats(lbdd_instance *h, int64_t *out, int32_t count) {
   int64_t sc[lbdd::SC_COUNT];
   HIP_TRY(hipStreamSynchronize(h->st), "hipStreamSynchronize");
   HIP_TRY(hipMemcpy(sc, h->scalars, sizeof sc, hipMemcpyDeviceToHost), "copy scalars");
-  const int m = count < lbdd::SC_NSTATS ? count : lbdd::SC_NSTATS;
-  for (int i = 0; i < m; ++i) out[i] = sc[lbdd::SC_STAT0 + i];
+  int64_t all[lbdd::SC_NSTATS + 1];
+  for (int i = 0; i < lbdd::SC_NSTATS; ++i) all[i] = sc[lbdd::SC_STAT0 + i];
+  int dev = 0, khz = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "clock rate");
+  all[lbdd::SC_NSTATS] = khz;
+  const int m = count < lbdd::SC_NSTATS + 1 ? count : lbdd::SC_NSTATS + 1;
+  for (int i = 0; i < m; ++i) out[i] = all[i];
   return m;
 }
 

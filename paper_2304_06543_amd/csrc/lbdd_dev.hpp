@@ -58,12 +58,14 @@ enum : int {
   SC_DONE = 1,          // iterations completed
   SC_STATUS = 2,        // 0 ok, else an LBDD_E_* code
   SC_STAT0 = 3,         // first of the counters reported by lbdd_stats
-  SC_NSTATS = 9,
+  SC_NSTATS = 13,
   SC_COUNT = SC_STAT0 + SC_NSTATS
 };
 enum : int {
   ST_CYCLES = 0, ST_PATHS, ST_MOVES, ST_CYC_SEARCH, ST_PATH_SEARCH, ST_BF_ROUNDS,
-  ST_ROWS_SCANNED, ST_ITERS, ST_CYC_SKIPPED
+  ST_ROWS_SCANNED, ST_ITERS, ST_CYC_SKIPPED,
+  // device wall-clock ticks spent in each phase (thread 0's view)
+  ST_T_ALLOT, ST_T_CYCLE, ST_T_PATH, ST_T_RESCAN
 };
 
 // ---- host launchers (return hipError_t) ----

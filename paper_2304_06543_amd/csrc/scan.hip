@@ -4,13 +4,17 @@
 //   W[u][v] = min over units d allotted to u of key(CM(d,v) - CM(d,u), rank(d)).
 //
 // HBM-bound streaming kernel.  Units are first grouped by their center (a
-// counting sort of the allotment into a list of (unit, rank) pairs), so that a
-// workgroup streams rows that all share one source center u and its partial
-// result is one row of k keys instead of a k x k table.  Lanes own column
-// quads (16-byte loads); per-lane running minima stay in registers for the
-// whole chunk, are combined across the workgroup with LDS atomics and leave
-// with one global atomic min per column per chunk.  Keys are unique, so the
-// result does not depend on the order in which rows or chunks are reduced.
+// counting sort of the allotment into a list of (unit, rank) pairs, ranked
+// inside each workgroup so that only one global atomic per center per
+// workgroup is needed).  The grouped list is then split into equal contiguous
+// shares, one per workgroup of a grid sized to fill the GPU once: a share
+// covers one or a few center segments, and within a segment every row has the
+// same source center u, so the partial result is one row of k keys instead of
+// a k x k table.  Lanes own column quads (16-byte loads); per-lane running
+// minima stay in registers over the segment, are combined across the
+// workgroup with LDS atomics and leave with one global atomic min per column
+// per segment.  Keys are unique, so the result does not depend on the order
+// in which rows or segments are reduced.
 #include "lbdd_dev.hpp"
 
 namespace lbdd {
@@ -18,7 +22,8 @@ namespace lbdd {
 namespace {
 
 constexpr int SCAN_THREADS = 256;
-constexpr int CHUNK_ROWS = 512;
+constexpr int SCATTER_THREADS = 1024;
+constexpr int SCATTER_ITEMS = 4;     // units per thread in the scatter pass
 
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -26,19 +31,16 @@ struct ScanWork {
   int32_t *count;      // [k]   units per center
   int32_t *cursor;     // [k]   scatter cursors
   int64_t *offset;     // [k+1] start of each center in the unit list
-  int64_t *chunk_off;  // [k+1] first chunk of each center
   int2 *units;         // [n]   (unit, rank) grouped by center
 };
 
-ScanWork carve(void *work, int32_t k, int64_t n) {
+ScanWork carve(void *work, int32_t k) {
   char *p = static_cast<char *>(work);
   ScanWork w;
   w.count = reinterpret_cast<int32_t *>(p); p += align_up((size_t)k * 4);
   w.cursor = reinterpret_cast<int32_t *>(p); p += align_up((size_t)k * 4);
   w.offset = reinterpret_cast<int64_t *>(p); p += align_up((size_t)(k + 1) * 8);
-  w.chunk_off = reinterpret_cast<int64_t *>(p); p += align_up((size_t)(k + 1) * 8);
   w.units = reinterpret_cast<int2 *>(p);
-  (void)n;
   return w;
 }
 
@@ -69,49 +71,58 @@ __global__ void histogram_kernel(int32_t k, int64_t n, const int32_t *__restrict
     if (h[i]) atomicAdd(&count[i], h[i]);
 }
 
-// exclusive prefix sums of the counts and of the per-center chunk counts
-// (k <= LBDD_MAX_K; one workgroup, sequential over 1024-wide blocks)
+// exclusive prefix sum of the counts (k <= LBDD_MAX_K; one workgroup)
 __global__ __launch_bounds__(1024) void offsets_kernel(int32_t k, const int32_t *__restrict__ count,
-                                                       int64_t *__restrict__ offset,
-                                                       int64_t *__restrict__ chunk_off) {
-  __shared__ int64_t a[1024], b[1024];
-  __shared__ int64_t carry_a, carry_b;
-  if (threadIdx.x == 0) { carry_a = 0; carry_b = 0; }
+                                                       int64_t *__restrict__ offset) {
+  __shared__ int64_t a[1024];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (int base = 0; base < k; base += 1024) {
     const int i = base + threadIdx.x;
     const int64_t c = i < k ? count[i] : 0;
     a[threadIdx.x] = c;
-    b[threadIdx.x] = (c + CHUNK_ROWS - 1) / CHUNK_ROWS;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {   // inclusive Hillis-Steele scan
       const int64_t va = threadIdx.x >= off ? a[threadIdx.x - off] : 0;
-      const int64_t vb = threadIdx.x >= off ? b[threadIdx.x - off] : 0;
       __syncthreads();
       a[threadIdx.x] += va;
-      b[threadIdx.x] += vb;
       __syncthreads();
     }
-    if (i < k) {
-      offset[i] = carry_a + a[threadIdx.x] - c;
-      chunk_off[i] = carry_b + b[threadIdx.x] - (c + CHUNK_ROWS - 1) / CHUNK_ROWS;
-    }
+    if (i < k) offset[i] = carry + a[threadIdx.x] - c;
     __syncthreads();
-    if (threadIdx.x == 0) { carry_a += a[1023]; carry_b += b[1023]; }
+    if (threadIdx.x == 0) carry += a[1023];
     __syncthreads();
   }
-  if (threadIdx.x == 0) { offset[k] = carry_a; chunk_off[k] = carry_b; }
+  if (threadIdx.x == 0) offset[k] = carry;
 }
 
-__global__ void scatter_kernel(int32_t k, int64_t n, const int32_t *__restrict__ assign,
-                               const int32_t *__restrict__ rank, const int64_t *__restrict__ offset,
-                               int32_t *__restrict__ cursor, int2 *__restrict__ units) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n; d += stride) {
-    const int32_t u = assign[d];
-    if (u < 0 || u >= k) continue;
-    const int32_t j = atomicAdd(&cursor[u], 1);
-    units[offset[u] + j] = make_int2((int32_t)d, rank[d]);
+// Group units by center.  Each workgroup ranks its own units per center in
+// LDS, reserves one range per center with a single global atomic, and writes.
+__global__ __launch_bounds__(SCATTER_THREADS) void scatter_kernel(
+    int32_t k, int64_t n, const int32_t *__restrict__ assign, const int32_t *__restrict__ rank,
+    const int64_t *__restrict__ offset, int32_t *__restrict__ cursor, int2 *__restrict__ units) {
+  extern __shared__ int32_t sh[];      // [k] local counts, then [k] local bases
+  int32_t *h = sh, *lbase = sh + k;
+  for (int i = threadIdx.x; i < k; i += SCATTER_THREADS) h[i] = 0;
+  __syncthreads();
+  const int64_t d0 = (int64_t)blockIdx.x * SCATTER_THREADS * SCATTER_ITEMS + threadIdx.x;
+  int32_t u[SCATTER_ITEMS], li[SCATTER_ITEMS];
+#pragma unroll
+  for (int j = 0; j < SCATTER_ITEMS; ++j) {
+    const int64_t d = d0 + (int64_t)j * SCATTER_THREADS;
+    u[j] = d < n ? assign[d] : -1;
+    li[j] = (u[j] >= 0 && u[j] < k) ? atomicAdd(&h[u[j]], 1) : -1;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += SCATTER_THREADS)
+    lbase[i] = h[i] ? atomicAdd(&cursor[i], h[i]) : 0;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < SCATTER_ITEMS; ++j) {
+    if (li[j] < 0) continue;
+    const int64_t d = d0 + (int64_t)j * SCATTER_THREADS;
+    units[offset[u[j]] + lbase[u[j]] + li[j]] = make_int2((int32_t)d, rank[d]);
   }
 }
 
@@ -119,130 +130,154 @@ __device__ inline uint64_t umin(uint64_t a, uint64_t b) { return b < a ? b : a; 
 
 // Lane layout: LPR lanes per row (a power of two <= 64), each lane owns NP
 // column groups of VEC consecutive columns: group q = lane_in_row + j*LPR.
+// Each row slot keeps two rows in flight.
 template <int VEC, int LPR, int NP>
 __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(int32_t k, const int32_t *__restrict__ cm,
                                                             const int2 *__restrict__ units,
                                                             const int64_t *__restrict__ offset,
-                                                            const int64_t *__restrict__ chunk_off,
                                                             uint64_t *__restrict__ W) {
   extern __shared__ uint64_t red[];   // [k]
-  const int64_t c = blockIdx.x;
-  // center of this chunk: largest u with chunk_off[u] <= c
-  int lo = 0, hi = k;   // invariant: chunk_off[lo] <= c < chunk_off[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (chunk_off[mid] <= c) lo = mid; else hi = mid;
+  const int64_t total = offset[k];
+  const int64_t b = blockIdx.x, G = gridDim.x;
+  const int64_t r_lo = total * b / G, r_hi = total * (b + 1) / G;
+  if (r_lo >= r_hi) return;
+  // center of row r_lo: largest u with offset[u] <= r_lo
+  int u;
+  {
+    int lo = 0, hi = k;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (offset[mid] <= r_lo) lo = mid; else hi = mid;
+    }
+    u = lo;
   }
-  const int u = lo;
-  const int64_t r0 = offset[u] + (c - chunk_off[u]) * CHUNK_ROWS;
-  int64_t r1 = r0 + CHUNK_ROWS;
-  if (r1 > offset[u + 1]) r1 = offset[u + 1];
-
-  for (int i = threadIdx.x; i < k; i += SCAN_THREADS) red[i] = KEY_NONE;
-
-  constexpr int SLOTS = SCAN_THREADS / LPR;        // rows processed side by side
+  constexpr int SLOTS = SCAN_THREADS / LPR;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
-  uint64_t best[NP][VEC];
+  int64_t seg = r_lo;
+  while (seg < r_hi) {
+    while (offset[u + 1] <= seg) ++u;            // skip centers with no units here
+    const int64_t seg_end = offset[u + 1] < r_hi ? offset[u + 1] : r_hi;
+    for (int i = threadIdx.x; i < k; i += SCAN_THREADS) red[i] = KEY_NONE;
+    uint64_t best[NP][VEC];
 #pragma unroll
-  for (int j = 0; j < NP; ++j)
+    for (int j = 0; j < NP; ++j)
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) best[j][e] = KEY_NONE;
-
-  for (int64_t r = r0 + slot; r < r1; r += SLOTS) {
-    const int2 ur = units[r];
-    const int32_t *row = cm + (int64_t)ur.x * k;
-    const uint32_t bias = 0x80000000u - (uint32_t)row[u];   // delta + 2^31 = v + bias
-    const uint64_t rk = (uint32_t)ur.y;
+      for (int e = 0; e < VEC; ++e) best[j][e] = KEY_NONE;
+    int64_t r = seg + slot;
+    for (; r + SLOTS < seg_end; r += 2 * SLOTS) {
+      const int2 ua = units[r], ub = units[r + SLOTS];
+      const int32_t *ra = cm + (int64_t)ua.x * k, *rb = cm + (int64_t)ub.x * k;
+      const uint32_t bias_a = 0x80000000u - (uint32_t)ra[u];
+      const uint32_t bias_b = 0x80000000u - (uint32_t)rb[u];
+#pragma unroll
+      for (int j = 0; j < NP; ++j) {
+        const int q = lane + j * LPR;
+        if (q * VEC >= k) break;
+        int32_t va[VEC], vb[VEC];
+        if constexpr (VEC == 4) {
+          const int4 ta = reinterpret_cast<const int4 *>(ra)[q];
+          const int4 tb = reinterpret_cast<const int4 *>(rb)[q];
+          va[0] = ta.x; va[1] = ta.y; va[2] = ta.z; va[3] = ta.w;
+          vb[0] = tb.x; vb[1] = tb.y; vb[2] = tb.z; vb[3] = tb.w;
+        } else {
+          va[0] = ra[q];
+          vb[0] = rb[q];
+        }
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          best[j][e] = umin(best[j][e], (uint64_t)((uint32_t)va[e] + bias_a) << 32 | (uint32_t)ua.y);
+          best[j][e] = umin(best[j][e], (uint64_t)((uint32_t)vb[e] + bias_b) << 32 | (uint32_t)ub.y);
+        }
+      }
+    }
+    if (r < seg_end) {
+      const int2 ua = units[r];
+      const int32_t *ra = cm + (int64_t)ua.x * k;
+      const uint32_t bias_a = 0x80000000u - (uint32_t)ra[u];
+#pragma unroll
+      for (int j = 0; j < NP; ++j) {
+        const int q = lane + j * LPR;
+        if (q * VEC >= k) break;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          best[j][e] = umin(best[j][e], (uint64_t)((uint32_t)ra[q * VEC + e] + bias_a) << 32 | (uint32_t)ua.y);
+      }
+    }
+    __syncthreads();                             // red initialised
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
       const int q = lane + j * LPR;
       if (q * VEC >= k) break;
-      int32_t v[VEC];
-      if (VEC == 4) {
-        const int4 t = reinterpret_cast<const int4 *>(row)[q];
-        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
-      } else {
-        v[0] = row[q];
-      }
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        const uint64_t key = (uint64_t)((uint32_t)v[e] + bias) << 32 | rk;
-        best[j][e] = umin(best[j][e], key);
-      }
+      for (int e = 0; e < VEC; ++e)
+        if (best[j][e] != KEY_NONE)
+          atomicMin((unsigned long long *)&red[q * VEC + e], (unsigned long long)best[j][e]);
     }
+    __syncthreads();
+    for (int v = threadIdx.x; v < k; v += SCAN_THREADS)
+      if (v != u && red[v] != KEY_NONE)
+        atomicMin((unsigned long long *)&W[(int64_t)u * k + v], (unsigned long long)red[v]);
+    __syncthreads();                             // red reused by the next segment
+    seg = seg_end;
   }
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < NP; ++j) {
-    const int q = lane + j * LPR;
-    if (q * VEC >= k) break;
-#pragma unroll
-    for (int e = 0; e < VEC; ++e)
-      if (best[j][e] != KEY_NONE)
-        atomicMin((unsigned long long *)&red[q * VEC + e], (unsigned long long)best[j][e]);
-  }
-  __syncthreads();
-  for (int v = threadIdx.x; v < k; v += SCAN_THREADS)
-    if (v != u && red[v] != KEY_NONE)
-      atomicMin((unsigned long long *)&W[(int64_t)u * k + v], (unsigned long long)red[v]);
 }
 
 template <int VEC, int LPR, int NP>
-hipError_t launch_scan_t(int32_t k, const int32_t *cm, const ScanWork &w, int64_t nchunks,
+hipError_t launch_scan_t(int32_t k, const int32_t *cm, const ScanWork &w, int blocks,
                          uint64_t *W, hipStream_t st) {
-  scan_kernel<VEC, LPR, NP><<<(unsigned)nchunks, SCAN_THREADS, (size_t)k * 8, st>>>(
-      k, cm, w.units, w.offset, w.chunk_off, W);
+  scan_kernel<VEC, LPR, NP><<<blocks, SCAN_THREADS, (size_t)k * 8, st>>>(k, cm, w.units, w.offset, W);
   return hipGetLastError();
 }
 
 template <int VEC>
-hipError_t dispatch_scan(int32_t k, const int32_t *cm, const ScanWork &w, int64_t nchunks,
+hipError_t dispatch_scan(int32_t k, const int32_t *cm, const ScanWork &w, int blocks,
                          uint64_t *W, hipStream_t st) {
   const int groups = (k + VEC - 1) / VEC;      // column groups per row
-  if (groups <= 1) return launch_scan_t<VEC, 1, 1>(k, cm, w, nchunks, W, st);
-  if (groups <= 2) return launch_scan_t<VEC, 2, 1>(k, cm, w, nchunks, W, st);
-  if (groups <= 4) return launch_scan_t<VEC, 4, 1>(k, cm, w, nchunks, W, st);
-  if (groups <= 8) return launch_scan_t<VEC, 8, 1>(k, cm, w, nchunks, W, st);
-  if (groups <= 16) return launch_scan_t<VEC, 16, 1>(k, cm, w, nchunks, W, st);
-  if (groups <= 32) return launch_scan_t<VEC, 32, 1>(k, cm, w, nchunks, W, st);
-  if (groups <= 64) return launch_scan_t<VEC, 64, 1>(k, cm, w, nchunks, W, st);
-  if (groups <= 128) return launch_scan_t<VEC, 64, 2>(k, cm, w, nchunks, W, st);
-  if (groups <= 256) return launch_scan_t<VEC, 64, 4>(k, cm, w, nchunks, W, st);
-  if (groups <= 512) return launch_scan_t<VEC, 64, 8>(k, cm, w, nchunks, W, st);
-  if (groups <= 1024) return launch_scan_t<VEC, 64, 16>(k, cm, w, nchunks, W, st);
-  return launch_scan_t<VEC, 64, 32>(k, cm, w, nchunks, W, st);
+  if (groups <= 1) return launch_scan_t<VEC, 1, 1>(k, cm, w, blocks, W, st);
+  if (groups <= 2) return launch_scan_t<VEC, 2, 1>(k, cm, w, blocks, W, st);
+  if (groups <= 4) return launch_scan_t<VEC, 4, 1>(k, cm, w, blocks, W, st);
+  if (groups <= 8) return launch_scan_t<VEC, 8, 1>(k, cm, w, blocks, W, st);
+  if (groups <= 16) return launch_scan_t<VEC, 16, 1>(k, cm, w, blocks, W, st);
+  if (groups <= 32) return launch_scan_t<VEC, 32, 1>(k, cm, w, blocks, W, st);
+  if (groups <= 64) return launch_scan_t<VEC, 64, 1>(k, cm, w, blocks, W, st);
+  if (groups <= 128) return launch_scan_t<VEC, 64, 2>(k, cm, w, blocks, W, st);
+  if (groups <= 256) return launch_scan_t<VEC, 64, 4>(k, cm, w, blocks, W, st);
+  if (groups <= 512) return launch_scan_t<VEC, 64, 8>(k, cm, w, blocks, W, st);
+  if (groups <= 1024) return launch_scan_t<VEC, 64, 16>(k, cm, w, blocks, W, st);
+  return launch_scan_t<VEC, 64, 32>(k, cm, w, blocks, W, st);
 }
 
 }  // namespace
 
 size_t scan_work_bytes(int32_t k, int64_t n) {
-  return 2 * align_up((size_t)k * 4) + 2 * align_up((size_t)(k + 1) * 8) + align_up((size_t)n * 8);
+  return 2 * align_up((size_t)k * 4) + align_up((size_t)(k + 1) * 8) + align_up((size_t)n * 8);
 }
-
-// Upper bound on the chunk count for n units over k centers.
-static int64_t max_chunks(int32_t k, int64_t n) { return n / CHUNK_ROWS + k; }
 
 hipError_t launch_full_scan(int32_t k, int64_t n, const int32_t *cm, const int32_t *assign,
                             const int32_t *rank, uint64_t *W, void *work, hipStream_t st) {
-  ScanWork w = carve(work, k, n);
+  ScanWork w = carve(work, k);
   hipError_t e;
   fill_kernel<<<256, 256, 0, st>>>((int64_t)k * k, KEY_NONE, W, k, w.count, w.cursor);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (n == 0) return hipSuccess;
   int64_t hb = (n + 1023) / 1024;
   if (hb > 2048) hb = 2048;
   histogram_kernel<<<(unsigned)hb, 1024, (size_t)k * 4, st>>>(k, n, assign, w.count);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  offsets_kernel<<<1, 1024, 0, st>>>(k, w.count, w.offset, w.chunk_off);
+  offsets_kernel<<<1, 1024, 0, st>>>(k, w.count, w.offset);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  scatter_kernel<<<(unsigned)hb, 1024, 0, st>>>(k, n, assign, rank, w.offset, w.cursor, w.units);
+  const int64_t per_block = (int64_t)SCATTER_THREADS * SCATTER_ITEMS;
+  scatter_kernel<<<(unsigned)((n + per_block - 1) / per_block), SCATTER_THREADS, (size_t)k * 8, st>>>(
+      k, n, assign, rank, w.offset, w.cursor, w.units);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // The chunk count is only known on the device; launch the upper bound and
-  // let surplus workgroups find an empty row range.
-  const int64_t nchunks = max_chunks(k, n);
+  // one resident wave of workgroups: 8 per CU
+  int dev = 0, cus = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  const int blocks = cus * 8;
   const bool vec = (k % 4 == 0) && ((uintptr_t)cm % 16 == 0);
-  return vec ? dispatch_scan<4>(k, cm, w, nchunks, W, st)
-             : dispatch_scan<1>(k, cm, w, nchunks, W, st);
+  return vec ? dispatch_scan<4>(k, cm, w, blocks, W, st) : dispatch_scan<1>(k, cm, w, blocks, W, st);
 }
 
 }  // namespace lbdd

@@ -32,20 +32,36 @@ namespace lbdd {
 namespace {
 
 constexpr int NT = 1024;
+constexpr int TILE = 1024;   // member rows staged per rescan pass (one per thread)
+constexpr int UNROLL = 8;    // member rows in flight per thread
+
+__device__ inline uint64_t umin(uint64_t a, uint64_t b) { return b < a ? b : a; }
+__device__ inline int64_t now() { return (int64_t)wall_clock64(); }
+
+// number of set bits of mask in lanes below this one
+__device__ inline int lanes_below(uint64_t mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
 
 struct Lds {
   uint64_t *W;      // [k][k] (LDS copy or the global table)
   uint64_t *red;    // [k+1] per-target minimum
   int64_t *dist;    // [k+1]
   int32_t *pred;    // [k+1]
-  int32_t *front0;  // [k+1] frontier lists (double-buffered)
+  int32_t *front0;  // [k+1] frontier lists (double-buffered) ...
   int32_t *front1;
+  int64_t *fdist0;  // [k+1] ... with the labels the nodes had when listed
+  int64_t *fdist1;
+  int64_t *pot;     // [k] node potentials (see refine)
   int32_t *load;    // [k]
   int32_t *cap;     // [k]
   int32_t *pen;     // [k]
   int32_t *mrow;    // [k+1] moved rows of the applied path
   int32_t *mfrom;   // [k+1]
   int32_t *mto;     // [k+1]
+  int32_t *trow;    // [TILE] member rows staged for a rescan
+  int32_t *tbase;   // [TILE] their cost at the rescanned center
 };
 
 struct Scalars {
@@ -54,7 +70,7 @@ struct Scalars {
   int32_t status;
   int32_t nfront[2];
   int32_t nmoves;
-  int32_t apply;
+  int32_t pot_ok;   // pot is feasible for the current W
   int32_t vacant;
 };
 
@@ -65,51 +81,70 @@ __device__ inline void lds_min(uint64_t *p, uint64_t v) {
 
 // Recompute row u of W from the members of center u (definition of Gamma):
 // W[u][w] = min over rows x at u of key(CM[x][w] - CM[x][u], x).
+// Members are taken TILE at a time: their row indices and their cost at u are
+// staged in LDS with one load per thread, then lane groups stream whole rows
+// with VEC-wide loads, UNROLL rows per thread in flight, keeping per-column
+// minima in registers; LDS atomics combine the row slots.
+template <int VEC>
 __device__ __forceinline__ void rescan_center(const InstView &I, const Lds &L, Scalars &S, int u) {
   const int k = I.k;
   const int tid = threadIdx.x;
   const int m = L.load[u];
   const int32_t *mem = I.members + (int64_t)u * I.n;
+  const int groups = (k + VEC - 1) / VEC;          // column groups per row
+  const int lpr = groups < NT ? groups : NT;       // lanes per row
+  const int slots = NT / lpr;                      // rows side by side
+  const int lane = tid % lpr, slot = tid / lpr;
   for (int w = tid; w < k; w += NT) L.red[w] = KEY_NONE;
-  __syncthreads();
-  if (k <= NT) {
-    const int G = NT / k;
-    const int w = tid % k, g = tid / k;
-    if (g < G && w != u) {
-      uint64_t best = KEY_NONE;
-      int i = g;
-      for (; i + 3 * G < m; i += 4 * G) {
-        const int32_t x0 = mem[i], x1 = mem[i + G], x2 = mem[i + 2 * G], x3 = mem[i + 3 * G];
-        const int32_t *r0 = I.cm + (int64_t)x0 * k, *r1 = I.cm + (int64_t)x1 * k;
-        const int32_t *r2 = I.cm + (int64_t)x2 * k, *r3 = I.cm + (int64_t)x3 * k;
-        const int32_t a0 = r0[w] - r0[u], a1 = r1[w] - r1[u];
-        const int32_t a2 = r2[w] - r2[u], a3 = r3[w] - r3[u];
-        uint64_t k0 = pack_key(a0, x0), k1 = pack_key(a1, x1);
-        uint64_t k2 = pack_key(a2, x2), k3 = pack_key(a3, x3);
-        k0 = k1 < k0 ? k1 : k0;
-        k2 = k3 < k2 ? k3 : k2;
-        k0 = k2 < k0 ? k2 : k0;
-        best = k0 < best ? k0 : best;
-      }
-      for (; i < m; i += G) {
-        const int32_t x = mem[i];
-        const int32_t *rx = I.cm + (int64_t)x * k;
-        uint64_t key = pack_key(rx[w] - rx[u], x);
-        best = key < best ? key : best;
-      }
-      lds_min(&L.red[w], best);
+  for (int t0 = 0; t0 < m; t0 += TILE) {
+    const int tn = (m - t0 < TILE) ? m - t0 : TILE;
+    __syncthreads();                               // previous tile consumed
+    if (tid < tn) {
+      const int32_t x = mem[t0 + tid];
+      L.trow[tid] = x;
+      L.tbase[tid] = I.cm[(int64_t)x * k + u];
     }
-  } else {
-    for (int w = tid; w < k; w += NT) {
-      if (w == u) continue;
-      uint64_t best = KEY_NONE;
-      for (int i = 0; i < m; ++i) {
-        const int32_t x = mem[i];
-        const int32_t *rx = I.cm + (int64_t)x * k;
-        uint64_t key = pack_key(rx[w] - rx[u], x);
-        best = key < best ? key : best;
+    __syncthreads();
+    if (slot >= slots) continue;
+    for (int q = lane; q < groups; q += lpr) {
+      uint64_t best[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) best[e] = KEY_NONE;
+      int i = slot;
+      for (; i + (UNROLL - 1) * slots < tn; i += UNROLL * slots) {
+        int32_t v[UNROLL][VEC];
+        uint32_t bias[UNROLL], rows[UNROLL];
+#pragma unroll
+        for (int j = 0; j < UNROLL; ++j) {
+          rows[j] = (uint32_t)L.trow[i + j * slots];
+          bias[j] = 0x80000000u - (uint32_t)L.tbase[i + j * slots];
+          const int32_t *rx = I.cm + (int64_t)rows[j] * k;
+          if constexpr (VEC == 4) {
+            const int4 t = reinterpret_cast<const int4 *>(rx)[q];
+            v[j][0] = t.x; v[j][1] = t.y; v[j][2] = t.z; v[j][3] = t.w;
+          } else {
+            v[j][0] = rx[q];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < UNROLL; ++j)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e)
+            best[e] = umin(best[e], (uint64_t)((uint32_t)v[j][e] + bias[j]) << 32 | rows[j]);
       }
-      L.red[w] = best;
+      for (; i < tn; i += slots) {
+        const uint32_t row = (uint32_t)L.trow[i];
+        const uint32_t bias = 0x80000000u - (uint32_t)L.tbase[i];
+        const int32_t *rx = I.cm + (int64_t)row * k;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          best[e] = umin(best[e], (uint64_t)((uint32_t)rx[q * VEC + e] + bias) << 32 | row);
+      }
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const int w = q * VEC + e;
+        if (w < k && w != u) lds_min(&L.red[w], best[e]);
+      }
     }
   }
   __syncthreads();
@@ -118,20 +153,50 @@ __device__ __forceinline__ void rescan_center(const InstView &I, const Lds &L, S
   __syncthreads();
 }
 
-// Min-insert row x's transfer keys into row v of W; returns (block-wide)
-// whether any entry strictly decreased.
+// Min-insert row x's transfer keys into row v of W.  Returns (block-wide)
+// bit 0: some entry strictly decreased; bit 1: a decreased entry breaks the
+// feasibility of the node potentials (reduced cost < 0).
 __device__ __forceinline__ int insert_row(const InstView &I, const Lds &L, int x, int v) {
   const int k = I.k;
   const int32_t *rx = I.cm + (int64_t)x * k;
   const int32_t base = rx[v];
-  int changed = 0;
+  int changed = 0, breaks = 0;
   for (int w = threadIdx.x; w < k; w += NT) {
     if (w == v) continue;
-    const uint64_t key = pack_key(rx[w] - base, (uint32_t)x);
+    const int32_t delta = rx[w] - base;
+    const uint64_t key = pack_key(delta, (uint32_t)x);
     uint64_t *p = &L.W[(int64_t)v * k + w];
-    if (key < *p) { *p = key; changed = 1; }
+    if (key < *p) {
+      *p = key;
+      changed = 1;
+      breaks |= L.pot[v] + delta < L.pot[w];
+    }
   }
-  return __syncthreads_or(changed);
+  const int c = __syncthreads_or(changed);
+  const int b = __syncthreads_or(breaks);
+  return c | (b << 1);
+}
+
+// After a search that applied nothing the labels are a feasible potential:
+// dist[v] <= dist[u] + W[u][v] holds for edges between centers by the
+// Bellman-Ford fixpoint (every center is reachable: the anchor holds at
+// least one unit, so it has an edge to every other center), and the edges
+// into the anchor need 0 <= dist[u] + W[u][s], i.e. no negative cycle through
+// s, which is checked here rather than assumed.
+__device__ __forceinline__ void adopt_potential(const InstView &I, const Lds &L, Scalars &S, int s) {
+  const int k = I.k;
+  int bad = 0;
+  for (int u = threadIdx.x; u < k; u += NT) {
+    if (u == s) continue;
+    if (L.dist[u] == DIST_NONE) { bad = 1; continue; }
+    const uint64_t key = L.W[(int64_t)u * k + s];
+    if (key != KEY_NONE && L.dist[u] + key_delta(key) < 0) bad = 1;
+  }
+  bad = __syncthreads_or(bad);
+  if (!bad)
+    for (int u = threadIdx.x; u < k; u += NT) L.pot[u] = (u == s) ? 0 : L.dist[u];
+  if (threadIdx.x == 0) S.pot_ok = !bad;
+  __syncthreads();
 }
 
 // Weight of edge u -> v on the split graph (node s = s_out, node k = s_in);
@@ -158,31 +223,45 @@ __device__ inline bool edge_weight(const InstView &I, const Lds &L, int s, int m
 }
 
 // Bellman-Ford from node s on the split graph; leaves dist/pred in LDS.
+// Two barriers per round: relax (frontier sources -> per-target minimum),
+// then update (strict improvement, next frontier, reset of the minima).
 // Returns false (and sets the status) on a change in round k+1.
 __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Scalars &S, int s, int mode) {
   const int k = I.k, K1 = k + 1;
   const int tid = threadIdx.x;
-  for (int v = tid; v < K1; v += NT) { L.dist[v] = DIST_NONE; L.pred[v] = -1; }
-  if (tid == 0) { S.nfront[0] = 1; S.nfront[1] = 0; }
+  for (int v = tid; v < K1; v += NT) {
+    L.dist[v] = (v == s) ? 0 : DIST_NONE;
+    L.pred[v] = -1;
+    L.red[v] = KEY_NONE;
+  }
+  if (tid == 0) { S.nfront[0] = 1; S.nfront[1] = 0; L.front0[0] = s; L.fdist0[0] = 0; }
   __syncthreads();
-  if (tid == 0) { L.dist[s] = 0; L.front0[0] = s; }
   int cur = 0;
   for (int t = 1; t <= K1; ++t) {
-    for (int v = tid; v < K1; v += NT) L.red[v] = KEY_NONE;
-    __syncthreads();
     const int nf = S.nfront[cur];
     const int32_t *F = cur ? L.front1 : L.front0;
+    const int64_t *FD = cur ? L.fdist1 : L.fdist0;
     if (K1 <= NT) {
       const int G = NT / K1;
       const int v = tid % K1, g = tid / K1;
       if (g < G && v != s) {
         uint64_t best = KEY_NONE;
-        for (int j = g; j < nf; j += G) {
-          const int u = F[j];
+        int j = g;
+        for (; j + 3 * G < nf; j += 4 * G) {
+          int u[4];
+          int64_t du[4], w[4];
+          bool e[4];
+#pragma unroll
+          for (int x = 0; x < 4; ++x) { u[x] = F[j + x * G]; du[x] = FD[j + x * G]; }
+#pragma unroll
+          for (int x = 0; x < 4; ++x) e[x] = edge_weight(I, L, s, mode, u[x], v, w[x]);
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
+            if (e[x]) best = umin(best, pack_cand(du[x] + w[x], u[x]));
+        }
+        for (; j < nf; j += G) {
           int64_t w;
-          if (!edge_weight(I, L, s, mode, u, v, w)) continue;
-          const uint64_t c = pack_cand(L.dist[u] + w, u);
-          best = c < best ? c : best;
+          if (edge_weight(I, L, s, mode, F[j], v, w)) best = umin(best, pack_cand(FD[j] + w, F[j]));
         }
         lds_min(&L.red[v], best);
       }
@@ -191,34 +270,46 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
         if (v == s) continue;
         uint64_t best = KEY_NONE;
         for (int j = 0; j < nf; ++j) {
-          const int u = F[j];
           int64_t w;
-          if (!edge_weight(I, L, s, mode, u, v, w)) continue;
-          const uint64_t c = pack_cand(L.dist[u] + w, u);
-          best = c < best ? c : best;
+          if (edge_weight(I, L, s, mode, F[j], v, w)) best = umin(best, pack_cand(FD[j] + w, F[j]));
         }
         L.red[v] = best;
       }
     }
     __syncthreads();
-    // update: strict improvement only; changed nodes form the next frontier
-    for (int v = tid; v < K1; v += NT) {
-      const uint64_t c = L.red[v];
-      if (c == KEY_NONE) continue;
-      const int64_t d = cand_dist(c);
-      if (d < L.dist[v]) {
-        L.dist[v] = d;
-        L.pred[v] = cand_node(c);
-        const int idx = atomicAdd(&S.nfront[cur ^ 1], 1);
-        (cur ? L.front0 : L.front1)[idx] = v;
+    int32_t *Fn = cur ? L.front0 : L.front1;
+    int64_t *FDn = cur ? L.fdist0 : L.fdist1;
+    for (int vb = 0; vb < K1; vb += NT) {
+      const int v = vb + tid;
+      bool ch = false;
+      if (v < K1) {
+        const uint64_t c = L.red[v];
+        if (c != KEY_NONE) {
+          L.red[v] = KEY_NONE;
+          const int64_t d = cand_dist(c);
+          if (d < L.dist[v]) {
+            L.dist[v] = d;
+            L.pred[v] = cand_node(c);
+            ch = true;
+          }
+        }
+      }
+      // one LDS atomic per wavefront for the frontier append
+      const uint64_t mask = __ballot(ch);
+      if (mask) {
+        int base = 0;
+        if ((tid & 63) == 0) base = atomicAdd(&S.nfront[cur ^ 1], __popcll(mask));
+        base = __shfl(base, 0);
+        if (ch) {
+          Fn[base + lanes_below(mask)] = v;
+          FDn[base + lanes_below(mask)] = L.dist[v];
+        }
       }
     }
     __syncthreads();
     const int nnext = S.nfront[cur ^ 1];
-    if (tid == 0) S.stats[ST_BF_ROUNDS] += 1;
-    __syncthreads();
+    if (tid == 0) { S.stats[ST_BF_ROUNDS] += 1; S.nfront[cur] = 0; }
     if (nnext == 0) return true;
-    if (tid == 0) S.nfront[cur] = 0;   // becomes the list after next
     cur ^= 1;
   }
   if (tid == 0) S.status = -5;   // LBDD_E_INTERNAL: negative cycle reachable
@@ -227,14 +318,19 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
 }
 
 // One refinement (mode 0: Algorithm 1, mode 1: Appendix A) anchored at s.
+template <bool WLDS, int VEC>
 __device__ __forceinline__ void refine(const InstView &I, const Lds &L, Scalars &S, int s, int mode) {
   const int k = I.k;
   const int tid = threadIdx.x;
   if (tid == 0) S.stats[mode == 0 ? ST_CYC_SEARCH : ST_PATH_SEARCH] += 1;
   if (!bellman_ford(I, L, S, s, mode)) return;
   const int64_t D = L.dist[k];
-  if (D == DIST_NONE || D >= 0) return;       // only strictly negative refinements apply
+  if (D == DIST_NONE || D >= 0) {             // only strictly negative refinements apply
+    adopt_potential(I, L, S, s);
+    return;
+  }
   if (tid == 0) {
+    S.pot_ok = 0;                             // W is about to change
     // walk back from s_in; node list is reversed (path[len-1] == s)
     int len = 0;
     int32_t *path = L.front0;                 // frontier lists are free now
@@ -279,12 +375,14 @@ __device__ __forceinline__ void refine(const InstView &I, const Lds &L, Scalars 
   }
   __syncthreads();
   const int nmov = S.nmoves;
-  for (int e = 0; e < nmov; ++e) rescan_center(I, L, S, L.mfrom[e]);
+  const int64_t t0 = now();
+  for (int e = 0; e < nmov; ++e) rescan_center<VEC>(I, L, S, L.mfrom[e]);
   if (mode == 1 && nmov > 0) insert_row(I, L, L.mrow[nmov - 1], L.mto[nmov - 1]);
+  if (tid == 0) S.stats[ST_T_RESCAN] += now() - t0;
   __syncthreads();
 }
 
-template <bool WLDS>
+template <bool WLDS, int VEC>
 __global__ __launch_bounds__(NT) void solve_kernel(InstView I, int64_t r_begin, int64_t r_end) {
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ Scalars S;
@@ -299,17 +397,27 @@ __global__ __launch_bounds__(NT) void solve_kernel(InstView I, int64_t r_begin, 
   L.pred = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
   L.front0 = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
   L.front1 = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
+  p = reinterpret_cast<unsigned char *>(((uintptr_t)p + 7) & ~(uintptr_t)7);
+  L.fdist0 = reinterpret_cast<int64_t *>(p); p += (size_t)K1 * 8;
+  L.fdist1 = reinterpret_cast<int64_t *>(p); p += (size_t)K1 * 8;
+  L.pot = reinterpret_cast<int64_t *>(p); p += (size_t)k * 8;
   L.load = reinterpret_cast<int32_t *>(p); p += (size_t)k * 4;
   L.cap = reinterpret_cast<int32_t *>(p); p += (size_t)k * 4;
   L.pen = reinterpret_cast<int32_t *>(p); p += (size_t)k * 4;
   L.mrow = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
   L.mfrom = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
-  L.mto = reinterpret_cast<int32_t *>(p);
+  L.mto = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
+  L.trow = reinterpret_cast<int32_t *>(p); p += (size_t)TILE * 4;
+  L.tbase = reinterpret_cast<int32_t *>(p);
 
   if (WLDS)
     for (int64_t i = tid; i < (int64_t)k * k; i += NT) L.W[i] = I.W[i];
+  for (int i = tid; i < k; i += NT) L.pot[i] = 0;
   for (int i = tid; i < k; i += NT) { L.load[i] = I.load[i]; L.cap[i] = I.cap[i]; L.pen[i] = I.pen[i]; }
   if (tid == 0) {
+    // the potential is not kept between launches: the first search rebuilds it
+    // (an empty table is certified by the zero potential)
+    S.pot_ok = r_begin == 0;
     S.obj = I.scalars[SC_OBJECTIVE];
     S.status = (int32_t)I.scalars[SC_STATUS];
     for (int j = 0; j < SC_NSTATS; ++j) S.stats[j] = I.scalars[SC_STAT0 + j];
@@ -319,6 +427,7 @@ __global__ __launch_bounds__(NT) void solve_kernel(InstView I, int64_t r_begin, 
   int64_t r = r_begin;
   if (ok0) {
     for (; r < r_end; ++r) {
+      const int64_t t0 = now();
       const int s = I.smin[r];
       const int32_t *row = I.cm + r * k;
       if (tid == 0) {
@@ -331,13 +440,25 @@ __global__ __launch_bounds__(NT) void solve_kernel(InstView I, int64_t r_begin, 
         L.load[s] = ld + 1;
         S.obj += (int64_t)row[s] + (vac ? 0 : L.pen[s]);
       }
-      const int changed = insert_row(I, L, (int)r, s);   // contains a barrier
-      if (changed) refine(I, L, S, s, 0);
+      const int ins = insert_row(I, L, (int)r, s);   // contains barriers
+      const int64_t t1 = now();
+      // Negative Cycle Refinement can only find something if the current W
+      // may hold a negative cycle: the insert lowered an entry and the node
+      // potentials no longer certify that W has none.
+      const bool search = (ins & 1) && (!S.pot_ok || (ins & 2));
+      if (search) refine<WLDS, VEC>(I, L, S, s, 0);
       else if (tid == 0) S.stats[ST_CYC_SKIPPED] += 1;
       __syncthreads();
+      const int64_t t2 = now();
       if (S.status != 0) break;
-      if (!S.vacant) refine(I, L, S, s, 1);
+      if (!S.vacant) refine<WLDS, VEC>(I, L, S, s, 1);
       __syncthreads();
+      if (tid == 0) {
+        const int64_t t3 = now();
+        S.stats[ST_T_ALLOT] += t1 - t0;
+        S.stats[ST_T_CYCLE] += t2 - t1;
+        S.stats[ST_T_PATH] += t3 - t2;
+      }
       if (S.status != 0) break;
     }
   }
@@ -357,7 +478,8 @@ __global__ __launch_bounds__(NT) void solve_kernel(InstView I, int64_t r_begin, 
 
 size_t solve_lds_bytes(int k, bool wlds) {
   const size_t K1 = (size_t)k + 1;
-  size_t b = K1 * 8 * 2 + K1 * 4 * 3 + (size_t)k * 4 * 3 + K1 * 4 * 3;
+  size_t b = K1 * 8 * 2 + K1 * 4 * 3 + 8 + K1 * 8 * 2 + (size_t)k * 8 + (size_t)k * 4 * 3 +
+             K1 * 4 * 3 + (size_t)TILE * 4 * 2;
   if (wlds) b += (size_t)k * k * 8;
   return b;
 }
@@ -397,25 +519,28 @@ hipError_t launch_unpermute(int64_t n, const int64_t *order, const int32_t *assi
 
 // W is kept in LDS when the whole per-instance LDS image fits next to the
 // static scalars (160 KB per CU on gfx950, a margin left for the compiler).
-constexpr size_t LDS_BUDGET = 150 * 1024;
+constexpr size_t LDS_BUDGET = 156 * 1024;
+
+template <bool WLDS, int VEC>
+static hipError_t launch_solve_t(const InstView &I, int64_t r_begin, int64_t r_end, size_t bytes,
+                                 hipStream_t st) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&solve_kernel<WLDS, VEC>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  solve_kernel<WLDS, VEC><<<1, NT, bytes, st>>>(I, r_begin, r_end);
+  return hipGetLastError();
+}
 
 hipError_t launch_solve(const InstView &I, int64_t r_begin, int64_t r_end, hipStream_t st) {
   if (r_end <= r_begin) return hipSuccess;
   const bool wlds = solve_lds_bytes(I.k, true) <= LDS_BUDGET;
   const size_t bytes = solve_lds_bytes(I.k, wlds);
-  hipError_t e;
-  if (wlds) {
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&solve_kernel<true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    solve_kernel<true><<<1, NT, bytes, st>>>(I, r_begin, r_end);
-  } else {
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&solve_kernel<false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    solve_kernel<false><<<1, NT, bytes, st>>>(I, r_begin, r_end);
-  }
-  return hipGetLastError();
+  // 16-byte row loads need rows that start on 16-byte boundaries
+  const bool vec = I.k % 4 == 0 && (uintptr_t)I.cm % 16 == 0;
+  if (wlds) return vec ? launch_solve_t<true, 4>(I, r_begin, r_end, bytes, st)
+                       : launch_solve_t<true, 1>(I, r_begin, r_end, bytes, st);
+  return vec ? launch_solve_t<false, 4>(I, r_begin, r_end, bytes, st)
+             : launch_solve_t<false, 1>(I, r_begin, r_end, bytes, st);
 }
 
 }  // namespace lbdd

@@ -23,7 +23,8 @@ CM_DEVICE = 0x1
 OUT_DEVICE = 0x1
 MAX_K = 2048
 STATS = ("cycles", "paths", "moves", "cycle_searches", "path_searches", "bf_rounds",
-         "rows_scanned", "iterations", "cycle_searches_skipped")
+         "rows_scanned", "iterations", "cycle_searches_skipped",
+         "ticks_allot", "ticks_cycle", "ticks_path", "ticks_rescan", "timer_khz")
 
 # every symbol include/lbdd.h declares
 EXPORTS = ("lbdd_create", "lbdd_solve", "lbdd_solve_iters", "lbdd_objective",
