@@ -126,6 +126,69 @@ int lbdd_snapshot(lbdd_instance *h, int32_t *load, uint64_t *W, int64_t *order);
  * Synchronises.  Returns the number of counters written (>= 0). */
 int lbdd_stats(lbdd_instance *h, int64_t *out, int32_t count);
 
+/* Solve many instances in one persistent launch (growth of Algorithm 2 to a
+ * batch of independent instances; each instance's result is the one
+ * lbdd_solve gives it alone).  Every workgroup of the launch is a worker that
+ * claims instances from a device-side queue, largest remaining work (n * k)
+ * first, and runs all their remaining iterations.
+ *   hs          m distinct handles (partially solved ones continue where they
+ *               stopped; solved ones are skipped)
+ *   hip_stream  stream of the launch; each instance's own stream is made to
+ *               wait for it, so later calls on a handle see its results
+ * Asynchronous.  Errors: LBDD_E_INVAL (NULL or repeated handles, m < 0),
+ * LBDD_E_NOMEM, LBDD_E_DEVICE. */
+int lbdd_solve_batch(lbdd_instance **hs, int32_t m, void *hip_stream);
+
+/* ---- request server (continuous batching on one GPU) ----------------------
+ * A server keeps a resident service kernel whose workers (one workgroup each,
+ * on all but `reserve_cus` compute units) solve admitted instances one after
+ * another; each result equals lbdd_solve's result for the instance alone.
+ * Requests are admitted in arrival order while their device footprint fits in
+ * the HBM budget and a job slot is free; younger requests that fit may pass an
+ * older one that does not, a bounded number of times in a row.  A request
+ * larger than the budget runs once nothing else is in flight.  Server calls
+ * are thread-safe. */
+typedef struct lbdd_server lbdd_server;
+
+enum { LBDD_JOB_QUEUED = 0, LBDD_JOB_RUNNING = 1, LBDD_JOB_DONE = 2 };
+
+/* hbm_budget: bytes of device memory jobs may hold at once (> 0);
+ * max_jobs: job slots (>= 1); reserve_cus: compute units left free for the
+ * setup kernels of newly admitted jobs.  Errors: LBDD_E_INVAL, LBDD_E_NOMEM,
+ * LBDD_E_DEVICE. */
+int lbdd_server_create(size_t hbm_budget, int32_t max_jobs, int32_t reserve_cus, lbdd_server **out);
+
+/* Queue one instance (arguments as lbdd_create with a host cost matrix).
+ * cm is borrowed: it must stay valid and unchanged until the job is finished
+ * (lbdd_server_poll reports LBDD_JOB_DONE or an error); capacity and penalty
+ * are copied.  *ticket identifies the job.  Errors: LBDD_E_INVAL,
+ * LBDD_E_STATE (server shutting down). */
+int lbdd_server_submit(lbdd_server *srv, int32_t k, int64_t n, const int32_t *cm,
+                       const int32_t *capacity, const int32_t *penalty, uint64_t *ticket);
+
+/* Non-blocking state of a job: LBDD_JOB_QUEUED, _RUNNING, _DONE, or a
+ * negative error code; *objective is set when done (may be NULL). */
+int lbdd_server_poll(lbdd_server *srv, uint64_t ticket, int32_t *state, int64_t *objective);
+
+/* Block until the job has finished; returns its error code if it failed. */
+int lbdd_server_wait(lbdd_server *srv, uint64_t ticket, int64_t *objective);
+
+/* Copy a finished job's allotment (n int32, host memory; may be NULL) and its
+ * times in seconds since the server started: times[0] submitted, [1] admitted
+ * (on the device and published to the workers), [2] finished (may be NULL).
+ * Releases the ticket.  Errors: LBDD_E_INVAL (unknown ticket), LBDD_E_STATE
+ * (not finished), or the job's own error. */
+int lbdd_server_result(lbdd_server *srv, uint64_t ticket, int32_t *assign, double *times);
+
+/* Counters (int64): [0] submitted [1] admitted [2] finished [3] failed
+ * [4] service kernel launches [5] peak jobs in flight [6] peak bytes admitted
+ * [7] bytes admitted now [8] workers.  Returns the number written. */
+int lbdd_server_stats(lbdd_server *srv, int64_t *out, int32_t count);
+
+/* Stop: waiting jobs are dropped (their state becomes LBDD_E_STATE), jobs
+ * already on the device finish, then everything is freed. */
+void lbdd_server_destroy(lbdd_server *srv);
+
 /* Free the instance and all its device memory (synchronises its stream). */
 void lbdd_destroy(lbdd_instance *h);
 

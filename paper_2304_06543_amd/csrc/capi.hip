@@ -7,49 +7,22 @@
 // between lbdd_create and the calls that return results.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/lbdd.h"
+#include "instance.hpp"
 #include "lbdd_dev.hpp"
-
-struct lbdd_instance {
-  int32_t k = 0;
-  int64_t n = 0;
-  hipStream_t st = nullptr;
-  int64_t enqueued = 0;                 // iterations launched so far
-  int32_t *cm = nullptr, *smin = nullptr, *cap = nullptr, *pen = nullptr;
-  int32_t *assign = nullptr, *load = nullptr, *members = nullptr, *slot = nullptr;
-  int32_t *unperm = nullptr;            // [n] staging for lbdd_assignment
-  int64_t *order = nullptr, *scalars = nullptr;
-  uint64_t *W = nullptr;
-
-  lbdd::InstView view() const {
-    lbdd::InstView v;
-    v.k = k; v.n = n; v.cm = cm; v.smin = smin; v.cap = cap; v.pen = pen;
-    v.assign = assign; v.load = load; v.members = members; v.slot = slot; v.W = W;
-    v.scalars = scalars;
-    return v;
-  }
-};
 
 namespace {
 
-thread_local std::string g_err;
-
-int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
-int fail(int code, const char *fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  g_err = buf;
-  return code;
-}
+using lbdd::fail;
+using lbdd::g_err;
 
 int hip_fail(hipError_t e, const char *what) {
   if (e == hipErrorOutOfMemory)
@@ -63,26 +36,36 @@ int hip_fail(hipError_t e, const char *what) {
     if (_e != hipSuccess) return hip_fail(_e, what); \
   } while (0)
 
+// All device memory of an instance is stream-ordered on the instance's
+// stream, and every copy is an async copy on that stream followed by a wait
+// for that stream only: nothing here waits for the whole device, so an
+// instance can be created, read and freed while other kernels (a batch or a
+// request server) keep running.
 template <class T>
-hipError_t dalloc(T **p, size_t count) {
-  return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T) + 1);
+hipError_t dalloc(T **p, size_t count, hipStream_t st) {
+  return hipMallocAsync(reinterpret_cast<void **>(p), count * sizeof(T) + 1, st);
+}
+
+hipError_t copy_sync(void *dst, const void *src, size_t bytes, hipMemcpyKind kind, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, st);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(st);
 }
 
 void release(lbdd_instance *h) {
   if (!h) return;
-  if (h->st) (void)hipStreamSynchronize(h->st);
-  else (void)hipDeviceSynchronize();
+  (void)hipStreamSynchronize(h->st);
   void *ptrs[] = {h->cm, h->smin, h->cap, h->pen, h->assign, h->load, h->members,
                   h->slot, h->unperm, h->order, h->scalars, h->W};
   for (void *p : ptrs)
-    if (p) (void)hipFree(p);
+    if (p) (void)hipFreeAsync(p, h->st);
+  (void)hipStreamSynchronize(h->st);
   delete h;
 }
 
 // Read the device scalars after the stream has drained.
 int read_scalars(lbdd_instance *h, int64_t *sc) {
-  HIP_TRY(hipStreamSynchronize(h->st), "hipStreamSynchronize");
-  HIP_TRY(hipMemcpy(sc, h->scalars, sizeof(int64_t) * lbdd::SC_COUNT, hipMemcpyDeviceToHost),
+  HIP_TRY(copy_sync(sc, h->scalars, sizeof(int64_t) * lbdd::SC_COUNT, hipMemcpyDeviceToHost, h->st),
           "copy scalars");
   if (sc[lbdd::SC_STATUS] != 0)
     return fail(LBDD_E_INTERNAL,
@@ -95,6 +78,22 @@ int read_scalars(lbdd_instance *h, int64_t *sc) {
 constexpr int64_t ITERS_PER_LAUNCH = 1 << 21;   // one launch covers every workload here
 
 }  // namespace
+
+namespace lbdd {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+}  // namespace lbdd
 
 extern "C" {
 
@@ -119,18 +118,18 @@ int lbdd_create(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity
   h->k = k; h->n = n; h->st = static_cast<hipStream_t>(hip_stream);
   const size_t nk = (size_t)n * (size_t)k;
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = dalloc(&h->cm, nk);
-  if (e == hipSuccess) e = dalloc(&h->smin, (size_t)n);
-  if (e == hipSuccess) e = dalloc(&h->cap, (size_t)k);
-  if (e == hipSuccess) e = dalloc(&h->pen, (size_t)k);
-  if (e == hipSuccess) e = dalloc(&h->assign, (size_t)n);
-  if (e == hipSuccess) e = dalloc(&h->load, (size_t)k);
-  if (e == hipSuccess) e = dalloc(&h->members, nk);
-  if (e == hipSuccess) e = dalloc(&h->slot, (size_t)n);
-  if (e == hipSuccess) e = dalloc(&h->unperm, (size_t)n);
-  if (e == hipSuccess) e = dalloc(&h->order, (size_t)n);
-  if (e == hipSuccess) e = dalloc(&h->scalars, (size_t)lbdd::SC_COUNT);
-  if (e == hipSuccess) e = dalloc(&h->W, (size_t)k * k);
+  if (e == hipSuccess) e = dalloc(&h->cm, nk, h->st);
+  if (e == hipSuccess) e = dalloc(&h->smin, (size_t)n, h->st);
+  if (e == hipSuccess) e = dalloc(&h->cap, (size_t)k, h->st);
+  if (e == hipSuccess) e = dalloc(&h->pen, (size_t)k, h->st);
+  if (e == hipSuccess) e = dalloc(&h->assign, (size_t)n, h->st);
+  if (e == hipSuccess) e = dalloc(&h->load, (size_t)k, h->st);
+  if (e == hipSuccess) e = dalloc(&h->members, nk, h->st);
+  if (e == hipSuccess) e = dalloc(&h->slot, (size_t)n, h->st);
+  if (e == hipSuccess) e = dalloc(&h->unperm, (size_t)n, h->st);
+  if (e == hipSuccess) e = dalloc(&h->order, (size_t)n, h->st);
+  if (e == hipSuccess) e = dalloc(&h->scalars, (size_t)lbdd::SC_COUNT, h->st);
+  if (e == hipSuccess) e = dalloc(&h->W, (size_t)k * k, h->st);
   if (e != hipSuccess) { release(h); return hip_fail(e, "device allocation"); }
 
   // setup scratch: the unpermuted CM (host input only), sort keys, a flag
@@ -140,14 +139,14 @@ int lbdd_create(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity
   int rc = LBDD_OK;
   do {
     if (!(flags & LBDD_CM_DEVICE)) {
-      if ((e = dalloc(&cm_tmp, nk)) != hipSuccess) { rc = hip_fail(e, "device allocation"); break; }
+      if ((e = dalloc(&cm_tmp, nk, h->st)) != hipSuccess) { rc = hip_fail(e, "device allocation"); break; }
       if ((e = hipMemcpyAsync(cm_tmp, cm, nk * 4, hipMemcpyHostToDevice, h->st)) != hipSuccess) {
         rc = hip_fail(e, "copy CM to device"); break;
       }
       cm_dev = cm_tmp;
     }
-    if ((e = hipMalloc(&work, lbdd::setup_work_bytes(k, n))) != hipSuccess) { rc = hip_fail(e, "device allocation"); break; }
-    if ((e = dalloc(&bad, 1)) != hipSuccess) { rc = hip_fail(e, "device allocation"); break; }
+    if ((e = hipMallocAsync(&work, lbdd::setup_work_bytes(k, n), h->st)) != hipSuccess) { rc = hip_fail(e, "device allocation"); break; }
+    if ((e = dalloc(&bad, 1, h->st)) != hipSuccess) { rc = hip_fail(e, "device allocation"); break; }
     int32_t zero = 0;
     if ((e = hipMemcpyAsync(bad, &zero, 4, hipMemcpyHostToDevice, h->st)) != hipSuccess) { rc = hip_fail(e, "init flag"); break; }
     if ((e = hipMemcpyAsync(h->cap, capacity, (size_t)k * 4, hipMemcpyHostToDevice, h->st)) != hipSuccess ||
@@ -165,10 +164,10 @@ int lbdd_create(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity
     }
     if (bad_h) rc = fail(LBDD_E_INVAL, "cost matrix has an entry outside [0, 2^30)");
   } while (0);
-  if (h->st) (void)hipStreamSynchronize(h->st);
-  if (cm_tmp) (void)hipFree(cm_tmp);
-  if (work) (void)hipFree(work);
-  if (bad) (void)hipFree(bad);
+  (void)hipStreamSynchronize(h->st);
+  if (cm_tmp) (void)hipFreeAsync(cm_tmp, h->st);
+  if (work) (void)hipFreeAsync(work, h->st);
+  if (bad) (void)hipFreeAsync(bad, h->st);
   if (rc != LBDD_OK) { release(h); return rc; }
   *out = h;
   return LBDD_OK;
@@ -219,7 +218,7 @@ int lbdd_assignment(lbdd_instance *h, int32_t *out, uint32_t flags) {
   int rc = read_scalars(h, sc);
   if (rc) return rc;
   if (!(flags & LBDD_OUT_DEVICE))
-    HIP_TRY(hipMemcpy(out, h->unperm, (size_t)h->n * 4, hipMemcpyDeviceToHost), "copy assignment");
+    HIP_TRY(copy_sync(out, h->unperm, (size_t)h->n * 4, hipMemcpyDeviceToHost, h->st), "copy assignment");
   return LBDD_OK;
 }
 
@@ -228,17 +227,16 @@ int lbdd_snapshot(lbdd_instance *h, int32_t *load, uint64_t *W, int64_t *order) 
   int64_t sc[lbdd::SC_COUNT];
   int rc = read_scalars(h, sc);
   if (rc) return rc;
-  if (load) HIP_TRY(hipMemcpy(load, h->load, (size_t)h->k * 4, hipMemcpyDeviceToHost), "copy load");
-  if (W) HIP_TRY(hipMemcpy(W, h->W, (size_t)h->k * h->k * 8, hipMemcpyDeviceToHost), "copy W");
-  if (order) HIP_TRY(hipMemcpy(order, h->order, (size_t)h->n * 8, hipMemcpyDeviceToHost), "copy order");
+  if (load) HIP_TRY(copy_sync(load, h->load, (size_t)h->k * 4, hipMemcpyDeviceToHost, h->st), "copy load");
+  if (W) HIP_TRY(copy_sync(W, h->W, (size_t)h->k * h->k * 8, hipMemcpyDeviceToHost, h->st), "copy W");
+  if (order) HIP_TRY(copy_sync(order, h->order, (size_t)h->n * 8, hipMemcpyDeviceToHost, h->st), "copy order");
   return LBDD_OK;
 }
 
 int lbdd_stats(lbdd_instance *h, int64_t *out, int32_t count) {
   if (!h || (!out && count > 0) || count < 0) return fail(LBDD_E_INVAL, "bad argument");
   int64_t sc[lbdd::SC_COUNT];
-  HIP_TRY(hipStreamSynchronize(h->st), "hipStreamSynchronize");
-  HIP_TRY(hipMemcpy(sc, h->scalars, sizeof sc, hipMemcpyDeviceToHost), "copy scalars");
+  HIP_TRY(copy_sync(sc, h->scalars, sizeof sc, hipMemcpyDeviceToHost, h->st), "copy scalars");
   int64_t all[lbdd::SC_NSTATS + 1];
   for (int i = 0; i < lbdd::SC_NSTATS; ++i) all[i] = sc[lbdd::SC_STAT0 + i];
   int dev = 0, khz = 0;
@@ -251,6 +249,63 @@ int lbdd_stats(lbdd_instance *h, int64_t *out, int32_t count) {
 }
 
 void lbdd_destroy(lbdd_instance *h) { release(h); }
+
+int lbdd_solve_batch(lbdd_instance **hs, int32_t m, void *hip_stream) {
+  g_err.clear();
+  if (m < 0 || (m > 0 && !hs)) return fail(LBDD_E_INVAL, "bad instance list");
+  if (m == 0) return LBDD_OK;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  std::vector<int32_t> idx;
+  for (int32_t i = 0; i < m; ++i) {
+    if (!hs[i]) return fail(LBDD_E_INVAL, "instance %d is NULL", i);
+    for (int32_t j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(LBDD_E_INVAL, "instance %d appears twice", i);
+    if (hs[i]->enqueued < hs[i]->n) idx.push_back(i);
+  }
+  if (idx.empty()) return LBDD_OK;
+  // largest remaining work first (longest-processing-time order)
+  std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) {
+    const double wa = (double)(hs[a]->n - hs[a]->enqueued) * hs[a]->k;
+    const double wb = (double)(hs[b]->n - hs[b]->enqueued) * hs[b]->k;
+    return wa > wb;
+  });
+  const int32_t mm = (int32_t)idx.size();
+  // device buffer: queue head (padded to 256 bytes), then the items
+  const size_t head_bytes = 256;
+  std::vector<unsigned char> host(head_bytes + sizeof(lbdd::BatchItem) * (size_t)mm, 0);
+  lbdd::BatchItem *items = reinterpret_cast<lbdd::BatchItem *>(host.data() + head_bytes);
+  for (int32_t i = 0; i < mm; ++i) {
+    items[i].inst = hs[idx[i]]->view();
+    items[i].r_begin = hs[idx[i]]->enqueued;
+  }
+  // the batch runs after whatever is pending on each instance's stream
+  hipEvent_t ev = nullptr;
+  HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+  for (int32_t i : idx) {
+    if (hs[i]->st == st) continue;
+    HIP_TRY(hipEventRecord(ev, hs[i]->st), "hipEventRecord");
+    HIP_TRY(hipStreamWaitEvent(st, ev, 0), "hipStreamWaitEvent");
+  }
+  void *dev = nullptr;
+  HIP_TRY(hipMallocAsync(&dev, host.size(), st), "device allocation");
+  HIP_TRY(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, st), "copy batch items");
+  HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");   // host buffer may go
+  const size_t lds = lbdd::batch_lds_bytes(items, mm);
+  const int workers = lbdd::batch_workers(lds, mm);
+  HIP_TRY(lbdd::launch_solve_batch(reinterpret_cast<const lbdd::BatchItem *>(
+                                       static_cast<unsigned char *>(dev) + head_bytes),
+                                   mm, static_cast<int32_t *>(dev), lds, workers, st),
+          "batch kernel launch");
+  HIP_TRY(hipFreeAsync(dev, st), "hipFreeAsync");
+  // later calls on each instance's own stream see the batch's results
+  HIP_TRY(hipEventRecord(ev, st), "hipEventRecord");
+  for (int32_t i : idx) {
+    hs[i]->enqueued = hs[i]->n;
+    if (hs[i]->st != st) HIP_TRY(hipStreamWaitEvent(hs[i]->st, ev, 0), "hipStreamWaitEvent");
+  }
+  HIP_TRY(hipEventDestroy(ev), "hipEventDestroy");
+  return LBDD_OK;
+}
 
 size_t lbdd_best_transfers_work_bytes(int32_t k, int64_t n) {
   if (k < 1 || n < 0) return 0;

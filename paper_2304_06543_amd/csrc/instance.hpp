@@ -1,0 +1,37 @@
+// instance.hpp -- host-side state of one LBDD instance (shared by the C ABI
+// translation units).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "lbdd_dev.hpp"
+
+namespace lbdd {
+// the calling thread's last failure, read by lbdd_last_error()
+extern thread_local std::string g_err;
+// record a failure description and return `code`
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+}  // namespace lbdd
+
+struct lbdd_instance {
+  int32_t k = 0;
+  int64_t n = 0;
+  hipStream_t st = nullptr;
+  int64_t enqueued = 0;                 // iterations launched so far
+  int32_t *cm = nullptr, *smin = nullptr, *cap = nullptr, *pen = nullptr;
+  int32_t *assign = nullptr, *load = nullptr, *members = nullptr, *slot = nullptr;
+  int32_t *unperm = nullptr;            // [n] staging for lbdd_assignment
+  int64_t *order = nullptr, *scalars = nullptr;
+  uint64_t *W = nullptr;
+
+  lbdd::InstView view() const {
+    lbdd::InstView v;
+    v.k = k; v.n = n; v.cm = cm; v.smin = smin; v.cap = cap; v.pen = pen;
+    v.assign = assign; v.load = load; v.members = members; v.slot = slot; v.W = W;
+    v.scalars = scalars;
+    return v;
+  }
+};
+

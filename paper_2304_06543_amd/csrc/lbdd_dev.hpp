@@ -68,6 +68,30 @@ enum : int {
   ST_T_ALLOT, ST_T_CYCLE, ST_T_PATH, ST_T_RESCAN
 };
 
+// one workgroup solves one instance
+constexpr int SOLVE_THREADS = 1024;
+constexpr int TILE_ROWS = 1024;            // member rows staged per rescan pass
+// W is kept in LDS when the whole per-instance LDS image fits (160 KB per CU
+// on gfx950, a margin left for static LDS)
+constexpr size_t LDS_BUDGET = 156 * 1024;
+__host__ __device__ size_t solve_lds_bytes(int k, bool wlds);
+
+// one instance of a batched launch
+struct BatchItem {
+  InstView inst;
+  int64_t r_begin;          // first iteration still to run
+};
+
+// Request server: control block and job ring in pinned host memory, shared
+// by the host server thread and the resident service kernel.
+struct ServiceCtl {
+  int64_t published;        // jobs published so far (host writes, release)
+  int64_t shutdown;         // nonzero: workers leave once no job is waiting
+};
+struct ServiceJob {
+  InstView inst;            // device state of the job's instance
+};
+
 // ---- host launchers (return hipError_t) ----
 // setup.hip: most suitable center, processing order, row permutation
 size_t setup_work_bytes(int32_t k, int64_t n);
@@ -79,6 +103,13 @@ hipError_t launch_init_state(const InstView &I, hipStream_t st);
 hipError_t launch_solve(const InstView &I, int64_t r_begin, int64_t r_end, hipStream_t st);
 hipError_t launch_unpermute(int64_t n, const int64_t *order, const int32_t *assign, int32_t *out,
                             hipStream_t st);
+size_t batch_lds_bytes(const BatchItem *items_host, int32_t m);
+int batch_workers(size_t lds_bytes, int32_t m);
+hipError_t launch_solve_batch(const BatchItem *items_dev, int32_t m, int32_t *head, size_t lds_bytes,
+                              int workers, hipStream_t st);
+int device_cus();
+hipError_t launch_service(ServiceCtl *ctl, const ServiceJob *ring, int32_t ring_size, int64_t *done,
+                          int64_t *head, int64_t idle_ticks, int workers, hipStream_t st);
 // scan.hip: whole-matrix best-transfer table
 size_t scan_work_bytes(int32_t k, int64_t n);
 hipError_t launch_full_scan(int32_t k, int64_t n, const int32_t *cm, const int32_t *assign,

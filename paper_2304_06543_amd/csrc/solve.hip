@@ -31,9 +31,9 @@ namespace lbdd {
 
 namespace {
 
-constexpr int NT = 1024;
-constexpr int TILE = 1024;   // member rows staged per rescan pass (one per thread)
-constexpr int UNROLL = 8;    // member rows in flight per thread
+constexpr int NT = SOLVE_THREADS;
+constexpr int TILE = TILE_ROWS;
+constexpr int UNROLL = 4;    // member rows in flight per thread (no spills at 1024 threads)
 
 __device__ inline uint64_t umin(uint64_t a, uint64_t b) { return b < a ? b : a; }
 __device__ inline int64_t now() { return (int64_t)wall_clock64(); }
@@ -73,6 +73,20 @@ struct Scalars {
   int32_t pot_ok;   // pot is feasible for the current W
   int32_t vacant;
 };
+
+}  // namespace
+
+// Dynamic LDS of one workgroup solving an instance with k centers, with or
+// without the k x k table in LDS.
+__host__ __device__ size_t solve_lds_bytes(int k, bool wlds) {
+  const size_t K1 = (size_t)k + 1;
+  size_t b = K1 * 8 * 2 + K1 * 4 * 3 + 8 + K1 * 8 * 2 + (size_t)k * 8 + (size_t)k * 4 * 3 +
+             K1 * 4 * 3 + (size_t)TILE_ROWS * 4 * 2;
+  if (wlds) b += (size_t)k * k * 8;
+  return b;
+}
+
+namespace {
 
 // Minimum of a per-thread candidate over each target, combined in LDS.
 __device__ inline void lds_min(uint64_t *p, uint64_t v) {
@@ -382,10 +396,10 @@ __device__ __forceinline__ void refine(const InstView &I, const Lds &L, Scalars 
   __syncthreads();
 }
 
+// Iterations [r_begin, r_end) of one instance by the calling workgroup.
 template <bool WLDS, int VEC>
-__global__ __launch_bounds__(NT) void solve_kernel(InstView I, int64_t r_begin, int64_t r_end) {
-  extern __shared__ __align__(16) unsigned char lds[];
-  __shared__ Scalars S;
+__device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, int64_t r_end,
+                                            unsigned char *lds, Scalars &S) {
   const int k = I.k, K1 = k + 1;
   const int tid = threadIdx.x;
   Lds L;
@@ -476,12 +490,41 @@ __global__ __launch_bounds__(NT) void solve_kernel(InstView I, int64_t r_begin, 
   }
 }
 
-size_t solve_lds_bytes(int k, bool wlds) {
-  const size_t K1 = (size_t)k + 1;
-  size_t b = K1 * 8 * 2 + K1 * 4 * 3 + 8 + K1 * 8 * 2 + (size_t)k * 8 + (size_t)k * 4 * 3 +
-             K1 * 4 * 3 + (size_t)TILE * 4 * 2;
-  if (wlds) b += (size_t)k * k * 8;
-  return b;
+template <bool WLDS, int VEC>
+__global__ __launch_bounds__(NT) void solve_kernel(InstView I, int64_t r_begin, int64_t r_end) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ Scalars S;
+  solve_range<WLDS, VEC>(I, r_begin, r_end, lds, S);
+}
+
+// Many instances in one launch: every workgroup is a worker that claims the
+// next instance from a device-side queue (items are ordered largest first by
+// the host) and runs all its remaining iterations, then claims again.  The
+// W placement and the load width are chosen per instance.
+__global__ __launch_bounds__(NT) void solve_batch_kernel(const BatchItem *__restrict__ items,
+                                                         int32_t m, int32_t *head,
+                                                         uint32_t lds_avail) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ Scalars S;
+  __shared__ int32_t claim;
+  for (;;) {
+    __syncthreads();                         // the previous instance is written back
+    if (threadIdx.x == 0) claim = atomicAdd(head, 1);
+    __syncthreads();
+    const int32_t c = __builtin_amdgcn_readfirstlane(claim);   // uniform: scalar loads below
+    if (c >= m) break;
+    const InstView I = items[c].inst;
+    const int64_t r0 = items[c].r_begin;
+    const bool wlds = solve_lds_bytes(I.k, true) <= lds_avail;
+    const bool vec = I.k % 4 == 0 && (uintptr_t)I.cm % 16 == 0;
+    if (wlds) {
+      if (vec) solve_range<true, 4>(I, r0, I.n, lds, S);
+      else solve_range<true, 1>(I, r0, I.n, lds, S);
+    } else {
+      if (vec) solve_range<false, 4>(I, r0, I.n, lds, S);
+      else solve_range<false, 1>(I, r0, I.n, lds, S);
+    }
+  }
 }
 
 }  // namespace
@@ -517,9 +560,6 @@ hipError_t launch_unpermute(int64_t n, const int64_t *order, const int32_t *assi
   return hipGetLastError();
 }
 
-// W is kept in LDS when the whole per-instance LDS image fits next to the
-// static scalars (160 KB per CU on gfx950, a margin left for the compiler).
-constexpr size_t LDS_BUDGET = 156 * 1024;
 
 template <bool WLDS, int VEC>
 static hipError_t launch_solve_t(const InstView &I, int64_t r_begin, int64_t r_end, size_t bytes,
@@ -529,6 +569,124 @@ static hipError_t launch_solve_t(const InstView &I, int64_t r_begin, int64_t r_e
   if (e != hipSuccess) return e;
   solve_kernel<WLDS, VEC><<<1, NT, bytes, st>>>(I, r_begin, r_end);
   return hipGetLastError();
+}
+
+namespace {
+
+// Resident worker loop of the request server.  A worker claims the oldest
+// published job that nobody has claimed (compare-and-swap on a device
+// counter, only ever below the published count, so no claim is lost), copies
+// its descriptor from pinned host memory, solves it, and signals completion
+// with a system-scope release store into pinned memory (so the host also sees
+// the job's results in device memory).  A worker leaves when shutdown is
+// requested or after idle_ticks of device time without a job; the host
+// launches the kernel again when new work arrives.
+__global__ __launch_bounds__(NT) void service_kernel(ServiceCtl *ctl, const ServiceJob *ring,
+                                                     int32_t ring_size, int64_t *done, int64_t *head,
+                                                     uint32_t lds_avail, int64_t idle_ticks) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ Scalars S;
+  __shared__ int64_t claim;
+  constexpr int WORDS = sizeof(InstView) / 4;
+  __shared__ uint32_t job[WORDS];
+  for (;;) {
+    __syncthreads();                           // previous job fully written back
+    if (threadIdx.x == 0) {
+      int64_t got = -1;
+      const int64_t t0 = now();
+      for (;;) {
+        const int64_t pub = __hip_atomic_load(&ctl->published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+        int64_t h = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (h < pub) {
+          if (__hip_atomic_compare_exchange_strong(head, &h, h + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT)) {
+            got = h;
+            break;
+          }
+          continue;
+        }
+        if (__hip_atomic_load(&ctl->shutdown, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+        if (now() - t0 > idle_ticks) break;
+        __builtin_amdgcn_s_sleep(64);
+      }
+      claim = got;
+      if (got >= 0) {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(&ring[got % ring_size].inst);
+        for (int i = 0; i < WORDS; ++i)
+          job[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+    __syncthreads();
+    const int64_t c = claim;
+    if (c < 0) break;
+    InstView I;
+    uint32_t *iw = reinterpret_cast<uint32_t *>(&I);
+#pragma unroll
+    for (int i = 0; i < WORDS; ++i) iw[i] = __builtin_amdgcn_readfirstlane(job[i]);
+    const bool wlds = solve_lds_bytes(I.k, true) <= lds_avail;
+    const bool vec = I.k % 4 == 0 && (uintptr_t)I.cm % 16 == 0;
+    if (wlds) {
+      if (vec) solve_range<true, 4>(I, 0, I.n, lds, S);
+      else solve_range<true, 1>(I, 0, I.n, lds, S);
+    } else {
+      if (vec) solve_range<false, 4>(I, 0, I.n, lds, S);
+      else solve_range<false, 1>(I, 0, I.n, lds, S);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_store(&done[c % ring_size], c + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+}  // namespace
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+  return cus > 0 ? cus : 1;
+}
+
+hipError_t launch_service(ServiceCtl *ctl, const ServiceJob *ring, int32_t ring_size, int64_t *done,
+                          int64_t *head, int64_t idle_ticks, int workers, hipStream_t st) {
+  const size_t lds = LDS_BUDGET;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&service_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  service_kernel<<<workers, NT, lds, st>>>(ctl, ring, ring_size, done, head, (uint32_t)lds, idle_ticks);
+  return hipGetLastError();
+}
+
+size_t batch_lds_bytes(const BatchItem *items_host, int32_t m) {
+  size_t b = 0;
+  for (int32_t i = 0; i < m; ++i) {
+    const int k = items_host[i].inst.k;
+    const size_t need = solve_lds_bytes(k, true) <= LDS_BUDGET ? solve_lds_bytes(k, true)
+                                                                : solve_lds_bytes(k, false);
+    b = need > b ? need : b;
+  }
+  return b;
+}
+
+hipError_t launch_solve_batch(const BatchItem *items_dev, int32_t m, int32_t *head, size_t lds_bytes,
+                              int workers, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&solve_batch_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  solve_batch_kernel<<<workers, NT, lds_bytes, st>>>(items_dev, m, head, (uint32_t)lds_bytes);
+  return hipGetLastError();
+}
+
+int batch_workers(size_t lds_bytes, int32_t m) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&solve_batch_kernel),
+                                                   NT, lds_bytes) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  const int w = cus * per_cu;
+  return m < w ? m : w;
 }
 
 hipError_t launch_solve(const InstView &I, int64_t r_begin, int64_t r_end, hipStream_t st) {

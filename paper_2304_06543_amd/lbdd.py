@@ -27,10 +27,15 @@ STATS = ("cycles", "paths", "moves", "cycle_searches", "path_searches", "bf_roun
          "ticks_allot", "ticks_cycle", "ticks_path", "ticks_rescan", "timer_khz")
 
 # every symbol include/lbdd.h declares
-EXPORTS = ("lbdd_create", "lbdd_solve", "lbdd_solve_iters", "lbdd_objective",
+EXPORTS = ("lbdd_create", "lbdd_solve", "lbdd_solve_iters", "lbdd_solve_batch", "lbdd_objective",
            "lbdd_assignment", "lbdd_progress", "lbdd_snapshot", "lbdd_stats",
            "lbdd_destroy", "lbdd_last_error", "lbdd_best_transfers_work_bytes",
-           "lbdd_best_transfers")
+           "lbdd_best_transfers", "lbdd_server_create", "lbdd_server_submit",
+           "lbdd_server_poll", "lbdd_server_wait", "lbdd_server_result", "lbdd_server_stats",
+           "lbdd_server_destroy")
+JOB_QUEUED, JOB_RUNNING, JOB_DONE = 0, 1, 2
+SERVER_STATS = ("submitted", "admitted", "finished", "failed", "kernel_launches",
+                "peak_jobs", "peak_bytes", "bytes_now", "workers")
 
 _lib = None
 
@@ -54,6 +59,7 @@ def load(path: str = LIB_PATH):
         "lbdd_create": ([I32, I64, P, P, P, U32, P, C.POINTER(P)], C.c_int),
         "lbdd_solve": ([P], C.c_int),
         "lbdd_solve_iters": ([P, I64], C.c_int),
+        "lbdd_solve_batch": ([C.POINTER(P), I32, P], C.c_int),
         "lbdd_objective": ([P, C.POINTER(I64)], C.c_int),
         "lbdd_assignment": ([P, P, U32], C.c_int),
         "lbdd_progress": ([P, C.POINTER(I64)], C.c_int),
@@ -63,6 +69,13 @@ def load(path: str = LIB_PATH):
         "lbdd_last_error": ([], C.c_char_p),
         "lbdd_best_transfers_work_bytes": ([I32, I64], C.c_size_t),
         "lbdd_best_transfers": ([I32, I64, P, P, P, P, P, P], C.c_int),
+        "lbdd_server_create": ([C.c_size_t, I32, I32, C.POINTER(P)], C.c_int),
+        "lbdd_server_submit": ([P, I32, I64, P, P, P, C.POINTER(C.c_uint64)], C.c_int),
+        "lbdd_server_poll": ([P, C.c_uint64, C.POINTER(I32), C.POINTER(I64)], C.c_int),
+        "lbdd_server_wait": ([P, C.c_uint64, C.POINTER(I64)], C.c_int),
+        "lbdd_server_result": ([P, C.c_uint64, P, P], C.c_int),
+        "lbdd_server_stats": ([P, P, I32], C.c_int),
+        "lbdd_server_destroy": ([P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -191,6 +204,14 @@ def solve(cm, capacity, penalty, stream=None):
         return inst.objective(), inst.assignment()
 
 
+def solve_batch(instances, stream=None):
+    """Solve a list of Instances in one persistent launch (lbdd_solve_batch)."""
+    lib = load()
+    arr = (C.c_void_p * len(instances))(*[i._h.value for i in instances])
+    _check(lib.lbdd_solve_batch(arr, len(instances), _stream_ptr(stream)))
+    return instances
+
+
 def best_transfers_work_bytes(k: int, n: int) -> int:
     return int(load().lbdd_best_transfers_work_bytes(int(k), int(n)))
 
@@ -214,3 +235,75 @@ def best_transfers(cm, assign, rank, W=None, work=None, stream=None):
                                       C.c_void_p(W.data_ptr()), C.c_void_p(work.data_ptr()),
                                       _stream_ptr(stream)))
     return W
+
+
+class Server:
+    """Request server with continuous batching (lbdd_server_*).
+
+    submit() keeps a reference to the cost matrix until the job's result has
+    been taken with result()."""
+
+    def __init__(self, hbm_budget: int = 64 << 30, max_jobs: int = 1024, reserve_cus: int = 16):
+        self._lib = load()
+        self._s = C.c_void_p()
+        _check(self._lib.lbdd_server_create(int(hbm_budget), int(max_jobs), int(reserve_cus),
+                                            C.byref(self._s)))
+        self._keep = {}
+
+    def submit(self, cm, capacity, penalty) -> int:
+        cmh = _host_i32(cm)
+        n, k = cmh.shape
+        cap, pen = _host_i32(capacity), _host_i32(penalty)
+        if cap.shape != (k,) or pen.shape != (k,):
+            raise ValueError("capacity and penalty need k entries")
+        t = C.c_uint64()
+        _check(self._lib.lbdd_server_submit(self._s, int(k), int(n), cmh.ctypes.data_as(C.c_void_p),
+                                            cap.ctypes.data_as(C.c_void_p),
+                                            pen.ctypes.data_as(C.c_void_p), C.byref(t)))
+        self._keep[t.value] = (cmh, n)
+        return t.value
+
+    def poll(self, ticket: int):
+        st, obj = C.c_int32(), C.c_int64()
+        _check(self._lib.lbdd_server_poll(self._s, int(ticket), C.byref(st), C.byref(obj)))
+        return st.value, (obj.value if st.value == JOB_DONE else None)
+
+    def wait(self, ticket: int) -> int:
+        obj = C.c_int64()
+        _check(self._lib.lbdd_server_wait(self._s, int(ticket), C.byref(obj)))
+        return obj.value
+
+    def result(self, ticket: int):
+        """(allotment int32[n], times (submitted, admitted, finished) in s)."""
+        _, n = self._keep[ticket]
+        a = np.empty(n, np.int32)
+        times = np.zeros(3, np.float64)
+        try:
+            _check(self._lib.lbdd_server_result(self._s, int(ticket), a.ctypes.data_as(C.c_void_p),
+                                                times.ctypes.data_as(C.c_void_p)))
+        finally:
+            self._keep.pop(ticket, None)
+        return a, tuple(times)
+
+    def stats(self) -> dict:
+        out = np.zeros(len(SERVER_STATS), np.int64)
+        m = _check(self._lib.lbdd_server_stats(self._s, out.ctypes.data_as(C.c_void_p), len(SERVER_STATS)))
+        return {name: int(out[i]) for i, name in enumerate(SERVER_STATS[:m])}
+
+    def close(self):
+        if self._s:
+            self._lib.lbdd_server_destroy(self._s)
+            self._s = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,103 @@
+"""Request server (continuous batching): every job's result equals the plain
+single-instance result (and the oracle), whatever else is on the device."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import lbdd_inputs as L
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    import paper_2304_06543_amd.lbdd as lb
+    lb.load()
+    assert torch.cuda.is_available()
+    return lb
+
+
+def mixed(count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(count):
+        k = int(rng.choice([2, 8, 20, 64, 100, 140, 300]))
+        n = int(rng.integers(1, 3000))
+        out.append(L.random_small(k=k, n=n, seed=50_000 + 100 * seed + j, cm_hi=int(rng.choice([5, 500])),
+                                  cap=["tight", "zero", 4][j % 3], pen_hi=400))
+    return out
+
+
+def test_results_in_the_mix_equal_alone(lb):
+    insts = mixed(20, 1)
+    refs = [oracle.solve(*i.arrays()) for i in insts]
+    rng = np.random.default_rng(0)
+    with lb.Server(hbm_budget=8 << 30, max_jobs=64) as srv:
+        tickets = []
+        for i in insts:
+            tickets.append(srv.submit(*i.arrays()))
+            time.sleep(float(rng.uniform(0, 0.01)))      # arrivals while others run
+        for inst, t, ref in zip(insts, tickets, refs):
+            say("server job", inst.name)
+            assert srv.wait(t) == ref.objective, inst.name
+            a, times = srv.result(t)
+            assert np.array_equal(a, ref.assign), inst.name
+            assert times[0] <= times[1] <= times[2]
+        st = srv.stats()
+        say("server stats", st)
+        assert st["finished"] == len(insts) and st["failed"] == 0
+
+
+def test_tiny_budget_runs_one_at_a_time(lb):
+    insts = mixed(6, 2)
+    with lb.Server(hbm_budget=1, max_jobs=8) as srv:
+        ts = [srv.submit(*i.arrays()) for i in insts]
+        for inst, t in zip(insts, ts):
+            ref = oracle.solve(*inst.arrays())
+            assert srv.wait(t) == ref.objective
+            assert np.array_equal(srv.result(t)[0], ref.assign)
+        assert srv.stats()["peak_jobs"] == 1
+
+
+def test_workers_relaunch_after_idle(lb):
+    insts = mixed(2, 3)
+    with lb.Server(hbm_budget=1 << 30, max_jobs=4) as srv:
+        t = srv.submit(*insts[0].arrays())
+        srv.wait(t)
+        srv.result(t)
+        time.sleep(0.6)                                   # workers leave when idle
+        t = srv.submit(*insts[1].arrays())
+        ref = oracle.solve(*insts[1].arrays())
+        assert srv.wait(t) == ref.objective
+        srv.result(t)
+        assert srv.stats()["kernel_launches"] >= 2
+
+
+def test_failed_job_is_reported(lb):
+    bad = np.ones((20, 3), np.int32)
+    bad[3, 1] = -1
+    good = L.random_small(k=3, n=20, seed=5)
+    with lb.Server(hbm_budget=1 << 30, max_jobs=4) as srv:
+        tb = srv.submit(bad, np.ones(3), np.ones(3))
+        tg = srv.submit(*good.arrays())
+        with pytest.raises(lb.LbddError) as e:
+            srv.wait(tb)
+        assert e.value.code == lb.E_INVAL
+        assert srv.wait(tg) == oracle.solve(*good.arrays()).objective
+        assert srv.stats()["failed"] == 1
+
+
+def test_destroy_with_waiting_jobs(lb):
+    insts = mixed(5, 4)
+    srv = lb.Server(hbm_budget=1, max_jobs=2)
+    for i in insts:
+        srv.submit(*i.arrays())
+    srv.close()                                           # must not hang
