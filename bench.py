@@ -14,6 +14,9 @@ Prints one JSON line.  Extra objects:
                 peak, timed with HIP events on the stream it runs on
   scan          the whole-matrix best-transfer scan at k=500, n=1,000,000
                 (2 GB of costs) against HBM peak
+  batch         batched launch vs plain solves on a subset of the batched
+                workload (solves/s, completion latency p50/p99)
+  serve         request server vs plain FIFO on a Poisson trace (--serve N)
   cpu_baseline  the CPU oracle timed on this host for one whole solve
 """
 import argparse
@@ -32,10 +35,102 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def solve_bytes(k: int, iters: int, rows_scanned: int) -> int:
-    """Algorithmic cost-matrix bytes of one solve: one CM row per allotment
-    plus, per rescanned member row, the row and its member-list entry."""
-    return iters * 4 * k + rows_scanned * (4 * k + 4)
+def solve_bytes(k: int, stats: dict) -> int:
+    """Algorithmic cost-matrix bytes of one solve: one CM row per allotment,
+    the moved unit's row twice per move (it leaves one center's lists and
+    joins another's), and per member row read by a list refill its list entry,
+    its cost at the center and its cost at the refilled column."""
+    return stats["iterations"] * 4 * k + stats["moves"] * 8 * k + stats["rows_scanned"] * 12
+
+
+def run_batch(m, lbdd, L, torch, dev):
+    """The first m instances of the batched workload (k ~ U{16..256}, n
+    log-uniform in [1e4, 2e5]): one lbdd_solve_batch launch against m plain
+    solves one after another, on the same GPU and the same device inputs."""
+    import numpy as np
+    specs = L.batch_specs()[:m]
+    insts = [L.make_batch_instance(sp) for sp in specs]
+    cms = [torch.from_numpy(i.cm).to(dev) for i in insts]
+    torch.cuda.synchronize()
+    log(f"bench: batch of {m}: plain solves one after another")
+    t0 = time.perf_counter()
+    plain_obj = []
+    for c, i in zip(cms, insts):
+        with lbdd.Instance(c, i.cap, i.pen) as h:
+            h.solve()
+            plain_obj.append(h.objective())
+    seq_s = time.perf_counter() - t0
+    log(f"bench: batch of {m}: one batched launch")
+    hs = [lbdd.Instance(c, i.cap, i.pen) for c, i in zip(cms, insts)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lbdd.solve_batch(hs)
+    objs = [h.objective() for h in hs]
+    bat_s = time.perf_counter() - t0
+    st = [h.stats() for h in hs]
+    khz = st[0]["timer_khz"]
+    first = min(x["tick_first"] for x in st)
+    lat = np.array([(x["tick_last"] - first) / (khz * 1e3) for x in st])
+    for h in hs:
+        h.close()
+    log(f"bench: batch {bat_s:.2f} s vs plain {seq_s:.2f} s")
+    return {"workload": f"first {m} instances of the batched workload (k~U{{16..256}}, "
+                        f"n log-uniform [1e4,2e5])",
+            "instances": m, "sum_nk": int(sum(i.n * i.k for i in insts)),
+            "batched_s": round(bat_s, 3), "plain_sequential_s": round(seq_s, 3),
+            "batched_solves_per_s": round(m / bat_s, 3),
+            "plain_solves_per_s": round(m / seq_s, 3), "speedup": round(seq_s / bat_s, 2),
+            "latency_from_launch_p50_s": round(float(np.percentile(lat, 50)), 3),
+            "latency_from_launch_p99_s": round(float(np.percentile(lat, 99)), 3),
+            "identical_to_plain": objs == plain_obj}
+
+
+def run_serve(count, max_n, max_k, lbdd, L):
+    """A Poisson arrival trace (mean gap 20 ms) replayed through the request
+    server (continuous batching) and through plain FIFO solves, one at a time
+    as they arrive; latency runs from arrival to result ready."""
+    import numpy as np
+    trace = L.serving_trace(count=count, n_range=(2000, max_n), k_range=(8, max_k))
+    insts = [L.gmm_manhattan(k, n, seed=sd, cap_frac=0.95, pen_lo=100, pen_hi=1000)
+             for _, (k, n, sd) in trace]
+    arr = [a for a, _ in trace]
+    log(f"bench: serving {count} requests")
+    with lbdd.Server(hbm_budget=96 << 30, max_jobs=1024) as srv:
+        t0 = time.perf_counter()
+        tickets = []
+        for a, inst in zip(arr, insts):
+            d = a - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            tickets.append(srv.submit(*inst.arrays()))
+        lat, objs = [], []
+        for tk in tickets:
+            objs.append(srv.wait(tk))
+            _, times = srv.result(tk)
+            lat.append(times[2] - times[0])
+        span = time.perf_counter() - t0
+        sst = srv.stats()
+    log("bench: plain FIFO replay")
+    t0 = time.perf_counter()
+    flat, fobjs = [], []
+    for a, inst in zip(arr, insts):
+        d = a - (time.perf_counter() - t0)
+        if d > 0:
+            time.sleep(d)
+        with lbdd.Instance(inst.cm, inst.cap, inst.pen) as h:
+            h.solve()
+            fobjs.append(h.objective())
+        flat.append((time.perf_counter() - t0) - a)
+    fspan = time.perf_counter() - t0
+    return {"workload": f"{count} Poisson arrivals at 50/s, k log-uniform [8,{max_k}], "
+                        f"n log-uniform [2000,{max_n}]",
+            "served_solves_per_s": round(count / span, 3),
+            "served_latency_p50_s": round(float(np.percentile(lat, 50)), 3),
+            "served_latency_p99_s": round(float(np.percentile(lat, 99)), 3),
+            "fifo_solves_per_s": round(count / fspan, 3),
+            "fifo_latency_p50_s": round(float(np.percentile(flat, 50)), 3),
+            "fifo_latency_p99_s": round(float(np.percentile(flat, 99)), 3),
+            "peak_jobs_on_device": sst["peak_jobs"], "identical_to_plain": objs == fobjs}
 
 
 def main():
@@ -46,6 +141,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-scan", action="store_true")
     ap.add_argument("--scan-reps", type=int, default=10)
+    ap.add_argument("--batch", type=int, default=16,
+                    help="instances of the batched workload to compare batched vs plain (0: skip)")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="requests of a Poisson trace to serve vs plain FIFO (0: skip)")
+    ap.add_argument("--serve-max-n", type=int, default=200_000)
+    ap.add_argument("--serve-max-k", type=int, default=256)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
@@ -99,7 +202,7 @@ def main():
     log(f"bench: {ms_per_step:.1f} ms/step, solve kernel {np.mean(solve_ms):.1f} ms, "
         f"objective parity {parity}, stats {stats}")
 
-    nbytes = solve_bytes(inst.k, stats["iterations"], stats["rows_scanned"])
+    nbytes = solve_bytes(inst.k, stats)
     kern_s = float(np.mean(solve_ms)) / 1e3
     achieved = nbytes / kern_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
@@ -136,6 +239,19 @@ def main():
         log(f"bench: scan {ms:.3f} ms -> {scan['achieved']} GB/s")
         del cmb, W, work
 
+    if args.copy_calib:
+        src = torch.empty(1 << 28, dtype=torch.int32, device=dev)     # 1 GiB
+        src.fill_(1)
+        torch.cuda.synchronize()
+        dst = src.clone()
+        torch.cuda.synchronize()
+        log("bench: 1 GiB copy done (counter calibration)")
+        del src, dst
+
+    batch = run_batch(args.batch, lbdd, L, torch, dev) if args.batch > 0 else None
+    serve = (run_serve(args.serve, args.serve_max_n, args.serve_max_k, lbdd, L)
+             if args.serve > 0 else None)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -164,6 +280,8 @@ def main():
         "stats": stats,
         "roofline": roofline,
         "scan": scan,
+        "batch": batch,
+        "serve": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -120,9 +120,15 @@ int lbdd_snapshot(lbdd_instance *h, int32_t *load, uint64_t *W, int64_t *order);
  *   [3] cycle searches run  [4] path searches run  [5] Bellman-Ford rounds
  *   [6] rows rescanned  [7] iterations done  [8] cycle searches skipped
  *       because the allotment left the anchor's transfer costs unchanged
+ *   [6] counts member rows read by list refills (one column each)
  *   [9] .. [12] device timer ticks spent in: allotment, cycle refinement,
- *       path refinement, rescans after applied refinements (part of [10],[11])
- *   [13] device timer frequency in kHz
+ *       path refinement, list updates and refills after applied refinements
+ *       (part of [10], [11])
+ *   [13] best-transfer list refills (column scans of one center's members)
+ *   [14] device timer when the instance's first solve launch began, [15] when
+ *       its last iteration so far finished (device timer ticks)
+ *   [16] Bellman-Ford edge relaxations (sum over rounds of frontier x k)
+ *   [17] device timer frequency in kHz
  * Synchronises.  Returns the number of counters written (>= 0). */
 int lbdd_stats(lbdd_instance *h, int64_t *out, int32_t count);
 

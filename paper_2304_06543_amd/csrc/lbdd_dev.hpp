@@ -48,9 +48,17 @@ struct InstView {
   int32_t *load;           // [k] units per center
   int32_t *members;        // [k][n] rows allotted to each center (first load[u])
   int32_t *slot;           // [n] index of row r in its center's member list
-  uint64_t *W;             // [k][k] best-transfer table
+  uint64_t *W;             // [k][k] best-transfer table (heads of the lists below)
+  uint64_t *best;          // [k][k][BEST_M] smallest transfer keys of each pair
+  uint8_t *meta;           // [k][k] keys held (low 4 bits), every unit held (META_ALL)
   int64_t *scalars;        // [SC_COUNT] objective, progress, status, counters
 };
+
+// Bounded best-transfer lists (the paper's BestTransHeap of an ordered center
+// pair, truncated): the list of (u, w) holds the c <= BEST_M smallest keys
+// among the units now allotted to u, sorted, unused slots all ones.
+constexpr int BEST_M = 8;
+constexpr uint8_t META_ALL = 16;   // the list holds every unit of the center
 
 // layout of InstView::scalars
 enum : int {
@@ -58,19 +66,22 @@ enum : int {
   SC_DONE = 1,          // iterations completed
   SC_STATUS = 2,        // 0 ok, else an LBDD_E_* code
   SC_STAT0 = 3,         // first of the counters reported by lbdd_stats
-  SC_NSTATS = 13,
+  SC_NSTATS = 17,
   SC_COUNT = SC_STAT0 + SC_NSTATS
 };
 enum : int {
   ST_CYCLES = 0, ST_PATHS, ST_MOVES, ST_CYC_SEARCH, ST_PATH_SEARCH, ST_BF_ROUNDS,
   ST_ROWS_SCANNED, ST_ITERS, ST_CYC_SKIPPED,
   // device wall-clock ticks spent in each phase (thread 0's view)
-  ST_T_ALLOT, ST_T_CYCLE, ST_T_PATH, ST_T_RESCAN
+  ST_T_ALLOT, ST_T_CYCLE, ST_T_PATH, ST_T_RESCAN,
+  ST_REFILLS,           // list refills (column rescans)
+  ST_T_FIRST,           // device timer when the instance's first launch began
+  ST_T_LAST,            // device timer when its last iteration finished
+  ST_RELAX              // Bellman-Ford edge relaxations (frontier size x targets)
 };
 
 // one workgroup solves one instance
 constexpr int SOLVE_THREADS = 1024;
-constexpr int TILE_ROWS = 1024;            // member rows staged per rescan pass
 // W is kept in LDS when the whole per-instance LDS image fits (160 KB per CU
 // on gfx950, a margin left for static LDS)
 constexpr size_t LDS_BUDGET = 156 * 1024;

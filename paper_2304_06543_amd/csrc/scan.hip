@@ -130,7 +130,54 @@ __device__ inline uint64_t umin(uint64_t a, uint64_t b) { return b < a ? b : a; 
 
 // Lane layout: LPR lanes per row (a power of two <= 64), each lane owns NP
 // column groups of VEC consecutive columns: group q = lane_in_row + j*LPR.
-// Each row slot keeps two rows in flight.
+// Each row slot keeps ROWS rows in flight and prefetches the (unit, rank)
+// entries of its next ROWS rows while they load, so no iteration waits on a
+// dependent list load.
+typedef int v4i __attribute__((ext_vector_type(4)));   // native 16-byte vector
+// rows in flight per slot: at most 32 loaded values per lane (4 rows when a
+// lane holds at most 8 columns, e.g. k <= 512 with 16-byte loads)
+template <int VEC, int NP>
+constexpr int rows_in_flight() {
+  constexpr int r = 32 / (VEC * NP);
+  return r < 1 ? 1 : (r > 4 ? 4 : r);
+}
+
+template <int VEC, int LPR, int NP, int ROWS>
+__device__ inline void scan_rows(int32_t k, int u, const int32_t *__restrict__ cm, const int2 (&ur)[ROWS],
+                                 int nvalid, int lane, uint64_t (&best)[NP][VEC]) {
+  int32_t v[ROWS][NP][VEC];
+  uint32_t bias[ROWS];
+#pragma unroll
+  for (int t = 0; t < ROWS; ++t) {
+    if (t >= nvalid) break;
+    const int32_t *row = cm + (int64_t)ur[t].x * k;
+    bias[t] = 0x80000000u - (uint32_t)__builtin_nontemporal_load(row + u);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int q = lane + j * LPR;
+      if (q * VEC >= k) break;
+      if constexpr (VEC == 4) {
+        const v4i x = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(row) + q);
+        v[t][j][0] = x[0]; v[t][j][1] = x[1]; v[t][j][2] = x[2]; v[t][j][3] = x[3];
+      } else {
+        v[t][j][0] = __builtin_nontemporal_load(row + q);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < ROWS; ++t) {
+    if (t >= nvalid) break;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int q = lane + j * LPR;
+      if (q * VEC >= k) break;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+        best[j][e] = umin(best[j][e], (uint64_t)((uint32_t)v[t][j][e] + bias[t]) << 32 | (uint32_t)ur[t].y);
+    }
+  }
+}
+
 template <int VEC, int LPR, int NP>
 __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(int32_t k, const int32_t *__restrict__ cm,
                                                             const int2 *__restrict__ units,
@@ -152,6 +199,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(int32_t k, const int
     u = lo;
   }
   constexpr int SLOTS = SCAN_THREADS / LPR;
+  constexpr int ROWS = rows_in_flight<VEC, NP>();
+  constexpr int STEP = ROWS * SLOTS;
   const int lane = threadIdx.x % LPR;
   const int slot = threadIdx.x / LPR;
   int64_t seg = r_lo;
@@ -164,45 +213,21 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(int32_t k, const int
     for (int j = 0; j < NP; ++j)
 #pragma unroll
       for (int e = 0; e < VEC; ++e) best[j][e] = KEY_NONE;
+    int2 nxt[ROWS];
     int64_t r = seg + slot;
-    for (; r + SLOTS < seg_end; r += 2 * SLOTS) {
-      const int2 ua = units[r], ub = units[r + SLOTS];
-      const int32_t *ra = cm + (int64_t)ua.x * k, *rb = cm + (int64_t)ub.x * k;
-      const uint32_t bias_a = 0x80000000u - (uint32_t)ra[u];
-      const uint32_t bias_b = 0x80000000u - (uint32_t)rb[u];
 #pragma unroll
-      for (int j = 0; j < NP; ++j) {
-        const int q = lane + j * LPR;
-        if (q * VEC >= k) break;
-        int32_t va[VEC], vb[VEC];
-        if constexpr (VEC == 4) {
-          const int4 ta = reinterpret_cast<const int4 *>(ra)[q];
-          const int4 tb = reinterpret_cast<const int4 *>(rb)[q];
-          va[0] = ta.x; va[1] = ta.y; va[2] = ta.z; va[3] = ta.w;
-          vb[0] = tb.x; vb[1] = tb.y; vb[2] = tb.z; vb[3] = tb.w;
-        } else {
-          va[0] = ra[q];
-          vb[0] = rb[q];
-        }
+    for (int t = 0; t < ROWS; ++t)
+      nxt[t] = (r + t * SLOTS < seg_end) ? units[r + t * SLOTS] : make_int2(0, 0);
+    for (; r < seg_end; r += STEP) {
+      int2 cur[ROWS];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-          best[j][e] = umin(best[j][e], (uint64_t)((uint32_t)va[e] + bias_a) << 32 | (uint32_t)ua.y);
-          best[j][e] = umin(best[j][e], (uint64_t)((uint32_t)vb[e] + bias_b) << 32 | (uint32_t)ub.y);
-        }
-      }
-    }
-    if (r < seg_end) {
-      const int2 ua = units[r];
-      const int32_t *ra = cm + (int64_t)ua.x * k;
-      const uint32_t bias_a = 0x80000000u - (uint32_t)ra[u];
+      for (int t = 0; t < ROWS; ++t) cur[t] = nxt[t];
+      const int64_t rn = r + STEP;
 #pragma unroll
-      for (int j = 0; j < NP; ++j) {
-        const int q = lane + j * LPR;
-        if (q * VEC >= k) break;
-#pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          best[j][e] = umin(best[j][e], (uint64_t)((uint32_t)ra[q * VEC + e] + bias_a) << 32 | (uint32_t)ua.y);
-      }
+      for (int t = 0; t < ROWS; ++t)
+        nxt[t] = (rn + t * SLOTS < seg_end) ? units[rn + t * SLOTS] : make_int2(0, 0);
+      const int64_t left = (seg_end - r + SLOTS - 1) / SLOTS;
+      scan_rows<VEC, LPR, NP, ROWS>(k, u, cm, cur, left < ROWS ? (int)left : ROWS, lane, best);
     }
     __syncthreads();                             // red initialised
 #pragma unroll
@@ -223,29 +248,38 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(int32_t k, const int
   }
 }
 
+// One resident wave of workgroups: as many per CU as registers and LDS allow.
 template <int VEC, int LPR, int NP>
-hipError_t launch_scan_t(int32_t k, const int32_t *cm, const ScanWork &w, int blocks,
+hipError_t launch_scan_t(int32_t k, const int32_t *cm, const ScanWork &w, int cus,
                          uint64_t *W, hipStream_t st) {
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void *>(&scan_kernel<VEC, LPR, NP>), SCAN_THREADS, (size_t)k * 8);
+  if (e != hipSuccess) return e;
+  const int blocks = cus * (per_cu > 0 ? per_cu : 1);
   scan_kernel<VEC, LPR, NP><<<blocks, SCAN_THREADS, (size_t)k * 8, st>>>(k, cm, w.units, w.offset, W);
   return hipGetLastError();
 }
 
 template <int VEC>
-hipError_t dispatch_scan(int32_t k, const int32_t *cm, const ScanWork &w, int blocks,
+hipError_t dispatch_scan(int32_t k, const int32_t *cm, const ScanWork &w, int cus,
                          uint64_t *W, hipStream_t st) {
   const int groups = (k + VEC - 1) / VEC;      // column groups per row
-  if (groups <= 1) return launch_scan_t<VEC, 1, 1>(k, cm, w, blocks, W, st);
-  if (groups <= 2) return launch_scan_t<VEC, 2, 1>(k, cm, w, blocks, W, st);
-  if (groups <= 4) return launch_scan_t<VEC, 4, 1>(k, cm, w, blocks, W, st);
-  if (groups <= 8) return launch_scan_t<VEC, 8, 1>(k, cm, w, blocks, W, st);
-  if (groups <= 16) return launch_scan_t<VEC, 16, 1>(k, cm, w, blocks, W, st);
-  if (groups <= 32) return launch_scan_t<VEC, 32, 1>(k, cm, w, blocks, W, st);
-  if (groups <= 64) return launch_scan_t<VEC, 64, 1>(k, cm, w, blocks, W, st);
-  if (groups <= 128) return launch_scan_t<VEC, 64, 2>(k, cm, w, blocks, W, st);
-  if (groups <= 256) return launch_scan_t<VEC, 64, 4>(k, cm, w, blocks, W, st);
-  if (groups <= 512) return launch_scan_t<VEC, 64, 8>(k, cm, w, blocks, W, st);
-  if (groups <= 1024) return launch_scan_t<VEC, 64, 16>(k, cm, w, blocks, W, st);
-  return launch_scan_t<VEC, 64, 32>(k, cm, w, blocks, W, st);
+  if (groups <= 1) return launch_scan_t<VEC, 1, 1>(k, cm, w, cus, W, st);
+  if (groups <= 2) return launch_scan_t<VEC, 2, 1>(k, cm, w, cus, W, st);
+  if (groups <= 4) return launch_scan_t<VEC, 4, 1>(k, cm, w, cus, W, st);
+  if (groups <= 8) return launch_scan_t<VEC, 8, 1>(k, cm, w, cus, W, st);
+  if (groups <= 16) return launch_scan_t<VEC, 16, 1>(k, cm, w, cus, W, st);
+  if (groups <= 32) return launch_scan_t<VEC, 32, 1>(k, cm, w, cus, W, st);
+  if (groups <= 64) return launch_scan_t<VEC, 64, 1>(k, cm, w, cus, W, st);
+  if (groups <= 128) return launch_scan_t<VEC, 64, 2>(k, cm, w, cus, W, st);
+  if (groups <= 256) return launch_scan_t<VEC, 64, 4>(k, cm, w, cus, W, st);
+  if (groups <= 512 || VEC == 4) return launch_scan_t<VEC, 64, 8>(k, cm, w, cus, W, st);
+  if constexpr (VEC == 1) {   // k <= LBDD_MAX_K = 2048
+    if (groups <= 1024) return launch_scan_t<VEC, 64, 16>(k, cm, w, cus, W, st);
+    return launch_scan_t<VEC, 64, 32>(k, cm, w, cus, W, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -271,13 +305,11 @@ hipError_t launch_full_scan(int32_t k, int64_t n, const int32_t *cm, const int32
   scatter_kernel<<<(unsigned)((n + per_block - 1) / per_block), SCATTER_THREADS, (size_t)k * 8, st>>>(
       k, n, assign, rank, w.offset, w.cursor, w.units);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // one resident wave of workgroups: 8 per CU
   int dev = 0, cus = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-  const int blocks = cus * 8;
   const bool vec = (k % 4 == 0) && ((uintptr_t)cm % 16 == 0);
-  return vec ? dispatch_scan<4>(k, cm, w, blocks, W, st) : dispatch_scan<1>(k, cm, w, blocks, W, st);
+  return vec ? dispatch_scan<4>(k, cm, w, cus, W, st) : dispatch_scan<1>(k, cm, w, cus, W, st);
 }
 
 }  // namespace lbdd

@@ -12,9 +12,12 @@
 //             so no negative s_out -> s_in path exists.
 //   path      when s was full: Negative Path Refinement (Appendix A) on the
 //             NPath split graph (edges into s_in are penalty differences).
-//   apply     the units on the chosen path move; every center that lost a
-//             unit has its row of W recomputed from its members (the scan of
-//             the cost matrix), the path's last center min-inserts its new unit.
+//   apply     the units on the chosen path move.  W is the head of a bounded
+//             best-transfer list per ordered center pair (the BestTransHeap of
+//             the paper, truncated to its BEST_M smallest keys): leaving and
+//             joining units update the lists, and a list that runs empty while
+//             not holding every unit of its center is refilled by a column
+//             scan of the center's members in the cost matrix.
 //
 // Bellman-Ford runs in synchronous rounds.  Only nodes whose label changed in
 // the previous round are relaxed from: a node that did not change cannot give
@@ -32,8 +35,6 @@ namespace lbdd {
 namespace {
 
 constexpr int NT = SOLVE_THREADS;
-constexpr int TILE = TILE_ROWS;
-constexpr int UNROLL = 4;    // member rows in flight per thread (no spills at 1024 threads)
 
 __device__ inline uint64_t umin(uint64_t a, uint64_t b) { return b < a ? b : a; }
 __device__ inline int64_t now() { return (int64_t)wall_clock64(); }
@@ -60,8 +61,8 @@ struct Lds {
   int32_t *mrow;    // [k+1] moved rows of the applied path
   int32_t *mfrom;   // [k+1]
   int32_t *mto;     // [k+1]
-  int32_t *trow;    // [TILE] member rows staged for a rescan
-  int32_t *tbase;   // [TILE] their cost at the rescanned center
+  int32_t *trow;    // [k+1] columns to refill
+  uint64_t *wmin;   // [2][NT/64] per-wavefront minima of a refill round
 };
 
 struct Scalars {
@@ -70,6 +71,7 @@ struct Scalars {
   int32_t status;
   int32_t nfront[2];
   int32_t nmoves;
+  int32_t nrefill;
   int32_t pot_ok;   // pot is feasible for the current W
   int32_t vacant;
 };
@@ -81,7 +83,7 @@ struct Scalars {
 __host__ __device__ size_t solve_lds_bytes(int k, bool wlds) {
   const size_t K1 = (size_t)k + 1;
   size_t b = K1 * 8 * 2 + K1 * 4 * 3 + 8 + K1 * 8 * 2 + (size_t)k * 8 + (size_t)k * 4 * 3 +
-             K1 * 4 * 3 + (size_t)TILE_ROWS * 4 * 2;
+             K1 * 4 * 3 + K1 * 4 + 8 + 2 * (SOLVE_THREADS / 64) * 8;
   if (wlds) b += (size_t)k * k * 8;
   return b;
 }
@@ -93,84 +95,44 @@ __device__ inline void lds_min(uint64_t *p, uint64_t v) {
   if (v != KEY_NONE) atomicMin((unsigned long long *)p, (unsigned long long)v);
 }
 
-// Recompute row u of W from the members of center u (definition of Gamma):
-// W[u][w] = min over rows x at u of key(CM[x][w] - CM[x][u], x).
-// Members are taken TILE at a time: their row indices and their cost at u are
-// staged in LDS with one load per thread, then lane groups stream whole rows
-// with VEC-wide loads, UNROLL rows per thread in flight, keeping per-column
-// minima in registers; LDS atomics combine the row slots.
-template <int VEC>
-__device__ __forceinline__ void rescan_center(const InstView &I, const Lds &L, Scalars &S, int u) {
-  const int k = I.k;
-  const int tid = threadIdx.x;
-  const int m = L.load[u];
-  const int32_t *mem = I.members + (int64_t)u * I.n;
-  const int groups = (k + VEC - 1) / VEC;          // column groups per row
-  const int lpr = groups < NT ? groups : NT;       // lanes per row
-  const int slots = NT / lpr;                      // rows side by side
-  const int lane = tid % lpr, slot = tid / lpr;
-  for (int w = tid; w < k; w += NT) L.red[w] = KEY_NONE;
-  for (int t0 = 0; t0 < m; t0 += TILE) {
-    const int tn = (m - t0 < TILE) ? m - t0 : TILE;
-    __syncthreads();                               // previous tile consumed
-    if (tid < tn) {
-      const int32_t x = mem[t0 + tid];
-      L.trow[tid] = x;
-      L.tbase[tid] = I.cm[(int64_t)x * k + u];
-    }
-    __syncthreads();
-    if (slot >= slots) continue;
-    for (int q = lane; q < groups; q += lpr) {
-      uint64_t best[VEC];
+// ---- bounded best-transfer lists ----------------------------------------
+// W[u][w] is the head of the list of (u, w) (BEST_M smallest keys of the
+// units at u, see lbdd_dev.hpp).  Joining and leaving units update the lists;
+// a list that runs empty while some unit of u is not in it ("unknown") is
+// refilled by a column rescan over the members of u.  Lists are kept in
+// registers while they are updated: no indexing by run-time values.
+
+__device__ inline void list_load(const uint64_t *p, uint64_t (&a)[BEST_M]) {
+  const ulonglong2 *q = reinterpret_cast<const ulonglong2 *>(p);
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) best[e] = KEY_NONE;
-      int i = slot;
-      for (; i + (UNROLL - 1) * slots < tn; i += UNROLL * slots) {
-        int32_t v[UNROLL][VEC];
-        uint32_t bias[UNROLL], rows[UNROLL];
-#pragma unroll
-        for (int j = 0; j < UNROLL; ++j) {
-          rows[j] = (uint32_t)L.trow[i + j * slots];
-          bias[j] = 0x80000000u - (uint32_t)L.tbase[i + j * slots];
-          const int32_t *rx = I.cm + (int64_t)rows[j] * k;
-          if constexpr (VEC == 4) {
-            const int4 t = reinterpret_cast<const int4 *>(rx)[q];
-            v[j][0] = t.x; v[j][1] = t.y; v[j][2] = t.z; v[j][3] = t.w;
-          } else {
-            v[j][0] = rx[q];
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < UNROLL; ++j)
-#pragma unroll
-          for (int e = 0; e < VEC; ++e)
-            best[e] = umin(best[e], (uint64_t)((uint32_t)v[j][e] + bias[j]) << 32 | rows[j]);
-      }
-      for (; i < tn; i += slots) {
-        const uint32_t row = (uint32_t)L.trow[i];
-        const uint32_t bias = 0x80000000u - (uint32_t)L.tbase[i];
-        const int32_t *rx = I.cm + (int64_t)row * k;
-#pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          best[e] = umin(best[e], (uint64_t)((uint32_t)rx[q * VEC + e] + bias) << 32 | row);
-      }
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        const int w = q * VEC + e;
-        if (w < k && w != u) lds_min(&L.red[w], best[e]);
-      }
-    }
+  for (int i = 0; i < BEST_M / 2; ++i) {
+    const ulonglong2 t = q[i];
+    a[2 * i] = t.x;
+    a[2 * i + 1] = t.y;
   }
-  __syncthreads();
-  for (int w = tid; w < k; w += NT) L.W[(int64_t)u * k + w] = L.red[w];
-  if (tid == 0) S.stats[ST_ROWS_SCANNED] += m;
-  __syncthreads();
+}
+__device__ inline void list_store(uint64_t *p, const uint64_t (&a)[BEST_M]) {
+  ulonglong2 *q = reinterpret_cast<ulonglong2 *>(p);
+#pragma unroll
+  for (int i = 0; i < BEST_M / 2; ++i) q[i] = make_ulonglong2(a[2 * i], a[2 * i + 1]);
+}
+// merge q into the sorted list a (the largest entry falls off the end)
+__device__ inline void list_merge(uint64_t (&a)[BEST_M], uint64_t q) {
+  uint64_t prev = a[0];
+  a[0] = umin(a[0], q);
+#pragma unroll
+  for (int i = 1; i < BEST_M; ++i) {
+    const uint64_t cur = a[i];
+    const uint64_t hi = prev > q ? prev : q;     // max(q, old a[i-1])
+    a[i] = umin(cur, hi);
+    prev = cur;
+  }
 }
 
-// Min-insert row x's transfer keys into row v of W.  Returns (block-wide)
-// bit 0: some entry strictly decreased; bit 1: a decreased entry breaks the
-// feasibility of the node potentials (reduced cost < 0).
-__device__ __forceinline__ int insert_row(const InstView &I, const Lds &L, int x, int v) {
+// Unit x (row x) joins center v: its keys enter v's lists, row v of W follows.
+// Returns (block-wide) bit 0: some W entry decreased; bit 1: a decreased entry
+// breaks the node potentials.
+__device__ __forceinline__ int join_center(const InstView &I, const Lds &L, int x, int v) {
   const int k = I.k;
   const int32_t *rx = I.cm + (int64_t)x * k;
   const int32_t base = rx[v];
@@ -178,10 +140,25 @@ __device__ __forceinline__ int insert_row(const InstView &I, const Lds &L, int x
   for (int w = threadIdx.x; w < k; w += NT) {
     if (w == v) continue;
     const int32_t delta = rx[w] - base;
-    const uint64_t key = pack_key(delta, (uint32_t)x);
-    uint64_t *p = &L.W[(int64_t)v * k + w];
-    if (key < *p) {
-      *p = key;
+    const uint64_t q = pack_key(delta, (uint32_t)x);
+    const int64_t idx = (int64_t)v * k + w;
+    const uint8_t meta = I.meta[idx];
+    const int c = meta & 15;
+    const bool all = meta & META_ALL;
+    uint64_t a[BEST_M];
+    list_load(I.best + idx * BEST_M, a);
+    int below = 0;                                // held keys smaller than q
+#pragma unroll
+    for (int i = 0; i < BEST_M; ++i) below += a[i] < q;
+    // with every unit held q always enters; otherwise only in front of a held
+    // key (beyond the last held key an unheld unit may be smaller)
+    if (!(all || below < c)) continue;
+    list_merge(a, q);
+    list_store(I.best + idx * BEST_M, a);
+    const bool full = c == BEST_M;
+    I.meta[idx] = (uint8_t)((full ? BEST_M : c + 1) | (all && !full ? META_ALL : 0));
+    if (a[0] < L.W[idx]) {
+      L.W[idx] = a[0];
       changed = 1;
       breaks |= L.pot[v] + delta < L.pot[w];
     }
@@ -189,6 +166,113 @@ __device__ __forceinline__ int insert_row(const InstView &I, const Lds &L, int x
   const int c = __syncthreads_or(changed);
   const int b = __syncthreads_or(breaks);
   return c | (b << 1);
+}
+
+// Unit x leaves center u: its keys leave u's lists.  Lists that become
+// unknown are left for refill_center.
+__device__ __forceinline__ void leave_center(const InstView &I, const Lds &L, int x, int u) {
+  const int k = I.k;
+  const int32_t *rx = I.cm + (int64_t)x * k;
+  const int32_t base = rx[u];
+  for (int w = threadIdx.x; w < k; w += NT) {
+    if (w == u) continue;
+    const uint64_t q = pack_key(rx[w] - base, (uint32_t)x);
+    const int64_t idx = (int64_t)u * k + w;
+    const uint8_t meta = I.meta[idx];
+    const int c = meta & 15;
+    uint64_t a[BEST_M];
+    list_load(I.best + idx * BEST_M, a);
+    bool held = false;
+#pragma unroll
+    for (int i = 0; i < BEST_M; ++i) held |= a[i] == q;
+    if (!held) continue;                         // not among the c smallest: lists unchanged
+#pragma unroll
+    for (int i = 0; i < BEST_M - 1; ++i) a[i] = a[i] < q ? a[i] : a[i + 1];
+    a[BEST_M - 1] = KEY_NONE;
+    list_store(I.best + idx * BEST_M, a);
+    I.meta[idx] = (uint8_t)((c - 1) | (meta & META_ALL));
+    L.W[idx] = a[0];                             // stale if unknown; refill sets it
+  }
+  __syncthreads();
+}
+
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int mask) {
+  const uint32_t lo = __shfl_xor((uint32_t)v, mask, 64);
+  const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), mask, 64);
+  return (uint64_t)hi << 32 | lo;
+}
+
+// Refill the list of (u, w) from the members of u: the BEST_M smallest keys
+// (definition of Gamma), by per-thread top lists merged in BEST_M rounds of a
+// workgroup min (wavefront shuffles + one LDS exchange per round).
+__device__ __forceinline__ void refill_column(const InstView &I, const Lds &L, Scalars &S, int u, int w) {
+  const int k = I.k;
+  const int tid = threadIdx.x;
+  const int m = L.load[u];
+  const int32_t *mem = I.members + (int64_t)u * I.n;
+  uint64_t b[BEST_M];
+#pragma unroll
+  for (int i = 0; i < BEST_M; ++i) b[i] = KEY_NONE;
+  int i = tid;
+  for (; i + NT < m; i += 2 * NT) {              // two member rows in flight
+    const int32_t y0 = mem[i], y1 = mem[i + NT];
+    const int32_t *r0 = I.cm + (int64_t)y0 * k, *r1 = I.cm + (int64_t)y1 * k;
+    const int32_t d0 = r0[w] - r0[u], d1 = r1[w] - r1[u];
+    list_merge(b, pack_key(d0, (uint32_t)y0));
+    list_merge(b, pack_key(d1, (uint32_t)y1));
+  }
+  if (i < m) {
+    const int32_t y = mem[i];
+    const int32_t *ry = I.cm + (int64_t)y * k;
+    list_merge(b, pack_key(ry[w] - ry[u], (uint32_t)y));
+  }
+  const int wave = tid >> 6;
+  uint64_t out[BEST_M];
+#pragma unroll
+  for (int r = 0; r < BEST_M; ++r) {
+    uint64_t g = b[0];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) g = umin(g, shfl_xor_u64(g, off));
+    if ((tid & 63) == 0) L.wmin[(r & 1) * (NT / 64) + wave] = g;
+    __syncthreads();
+    uint64_t gm = KEY_NONE;
+#pragma unroll
+    for (int j = 0; j < NT / 64; ++j) gm = umin(gm, L.wmin[(r & 1) * (NT / 64) + j]);
+    out[r] = gm;
+    if (gm != KEY_NONE && b[0] == gm) {          // keys are unique: one owner pops
+#pragma unroll
+      for (int j = 0; j < BEST_M - 1; ++j) b[j] = b[j + 1];
+      b[BEST_M - 1] = KEY_NONE;
+    }
+  }
+  if (tid == 0) {
+    const int64_t idx = (int64_t)u * k + w;
+    list_store(I.best + idx * BEST_M, out);
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < BEST_M; ++j) c += out[j] != KEY_NONE;
+    I.meta[idx] = (uint8_t)(c | (m <= BEST_M ? META_ALL : 0));
+    L.W[idx] = out[0];
+    S.stats[ST_ROWS_SCANNED] += m;
+    S.stats[ST_REFILLS] += 1;
+  }
+  __syncthreads();
+}
+
+// Refill every unknown list of center u (after its unit left and the moves of
+// the refinement have all been applied).
+__device__ __forceinline__ void refill_center(const InstView &I, const Lds &L, Scalars &S, int u) {
+  const int k = I.k;
+  if (threadIdx.x == 0) S.nrefill = 0;
+  __syncthreads();
+  for (int w = threadIdx.x; w < k; w += NT) {
+    if (w == u) continue;
+    const uint8_t meta = I.meta[(int64_t)u * k + w];
+    if ((meta & 15) == 0 && !(meta & META_ALL)) L.trow[atomicAdd(&S.nrefill, 1)] = w;
+  }
+  __syncthreads();
+  const int nr = S.nrefill;
+  for (int j = 0; j < nr; ++j) refill_column(I, L, S, u, L.trow[j]);
 }
 
 // After a search that applied nothing the labels are a feasible potential:
@@ -322,7 +406,11 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
     }
     __syncthreads();
     const int nnext = S.nfront[cur ^ 1];
-    if (tid == 0) { S.stats[ST_BF_ROUNDS] += 1; S.nfront[cur] = 0; }
+    if (tid == 0) {
+      S.stats[ST_BF_ROUNDS] += 1;
+      S.stats[ST_RELAX] += (int64_t)nf * k;
+      S.nfront[cur] = 0;
+    }
     if (nnext == 0) return true;
     cur ^= 1;
   }
@@ -332,7 +420,7 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
 }
 
 // One refinement (mode 0: Algorithm 1, mode 1: Appendix A) anchored at s.
-template <bool WLDS, int VEC>
+template <bool WLDS>
 __device__ __forceinline__ void refine(const InstView &I, const Lds &L, Scalars &S, int s, int mode) {
   const int k = I.k;
   const int tid = threadIdx.x;
@@ -390,14 +478,17 @@ __device__ __forceinline__ void refine(const InstView &I, const Lds &L, Scalars 
   __syncthreads();
   const int nmov = S.nmoves;
   const int64_t t0 = now();
-  for (int e = 0; e < nmov; ++e) rescan_center<VEC>(I, L, S, L.mfrom[e]);
-  if (mode == 1 && nmov > 0) insert_row(I, L, L.mrow[nmov - 1], L.mto[nmov - 1]);
+  // every unit leaves its old center's lists before any joins the new ones;
+  // lists left unknown are refilled from the final members
+  for (int e = 0; e < nmov; ++e) leave_center(I, L, L.mrow[e], L.mfrom[e]);
+  for (int e = 0; e < nmov; ++e) join_center(I, L, L.mrow[e], L.mto[e]);
+  for (int e = 0; e < nmov; ++e) refill_center(I, L, S, L.mfrom[e]);
   if (tid == 0) S.stats[ST_T_RESCAN] += now() - t0;
   __syncthreads();
 }
 
 // Iterations [r_begin, r_end) of one instance by the calling workgroup.
-template <bool WLDS, int VEC>
+template <bool WLDS>
 __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, int64_t r_end,
                                             unsigned char *lds, Scalars &S) {
   const int k = I.k, K1 = k + 1;
@@ -421,8 +512,9 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
   L.mrow = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
   L.mfrom = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
   L.mto = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
-  L.trow = reinterpret_cast<int32_t *>(p); p += (size_t)TILE * 4;
-  L.tbase = reinterpret_cast<int32_t *>(p);
+  L.trow = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
+  p = reinterpret_cast<unsigned char *>(((uintptr_t)p + 7) & ~(uintptr_t)7);
+  L.wmin = reinterpret_cast<uint64_t *>(p);
 
   if (WLDS)
     for (int64_t i = tid; i < (int64_t)k * k; i += NT) L.W[i] = I.W[i];
@@ -436,6 +528,7 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
     S.status = (int32_t)I.scalars[SC_STATUS];
     for (int j = 0; j < SC_NSTATS; ++j) S.stats[j] = I.scalars[SC_STAT0 + j];
   }
+  if (tid == 0 && S.stats[ST_T_FIRST] == 0) S.stats[ST_T_FIRST] = now();
   __syncthreads();
   const bool ok0 = S.status == 0;
   int64_t r = r_begin;
@@ -454,18 +547,18 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
         L.load[s] = ld + 1;
         S.obj += (int64_t)row[s] + (vac ? 0 : L.pen[s]);
       }
-      const int ins = insert_row(I, L, (int)r, s);   // contains barriers
+      const int ins = join_center(I, L, (int)r, s);   // contains barriers
       const int64_t t1 = now();
       // Negative Cycle Refinement can only find something if the current W
       // may hold a negative cycle: the insert lowered an entry and the node
       // potentials no longer certify that W has none.
       const bool search = (ins & 1) && (!S.pot_ok || (ins & 2));
-      if (search) refine<WLDS, VEC>(I, L, S, s, 0);
+      if (search) refine<WLDS>(I, L, S, s, 0);
       else if (tid == 0) S.stats[ST_CYC_SKIPPED] += 1;
       __syncthreads();
       const int64_t t2 = now();
       if (S.status != 0) break;
-      if (!S.vacant) refine<WLDS, VEC>(I, L, S, s, 1);
+      if (!S.vacant) refine<WLDS>(I, L, S, s, 1);
       __syncthreads();
       if (tid == 0) {
         const int64_t t3 = now();
@@ -486,15 +579,16 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
     const int64_t done = (S.status == 0) ? r_end : r;   // r: iteration that failed
     I.scalars[SC_DONE] = ok0 ? done : I.scalars[SC_DONE];
     S.stats[ST_ITERS] = I.scalars[SC_DONE];
+    S.stats[ST_T_LAST] = now();
     for (int j = 0; j < SC_NSTATS; ++j) I.scalars[SC_STAT0 + j] = S.stats[j];
   }
 }
 
-template <bool WLDS, int VEC>
+template <bool WLDS>
 __global__ __launch_bounds__(NT) void solve_kernel(InstView I, int64_t r_begin, int64_t r_end) {
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ Scalars S;
-  solve_range<WLDS, VEC>(I, r_begin, r_end, lds, S);
+  solve_range<WLDS>(I, r_begin, r_end, lds, S);
 }
 
 // Many instances in one launch: every workgroup is a worker that claims the
@@ -516,14 +610,8 @@ __global__ __launch_bounds__(NT) void solve_batch_kernel(const BatchItem *__rest
     const InstView I = items[c].inst;
     const int64_t r0 = items[c].r_begin;
     const bool wlds = solve_lds_bytes(I.k, true) <= lds_avail;
-    const bool vec = I.k % 4 == 0 && (uintptr_t)I.cm % 16 == 0;
-    if (wlds) {
-      if (vec) solve_range<true, 4>(I, r0, I.n, lds, S);
-      else solve_range<true, 1>(I, r0, I.n, lds, S);
-    } else {
-      if (vec) solve_range<false, 4>(I, r0, I.n, lds, S);
-      else solve_range<false, 1>(I, r0, I.n, lds, S);
-    }
+    if (wlds) solve_range<true>(I, r0, I.n, lds, S);
+    else solve_range<false>(I, r0, I.n, lds, S);
   }
 }
 
@@ -535,7 +623,11 @@ __global__ void init_state_kernel(InstView I) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = t0; i < I.n; i += stride) I.assign[i] = -1;
-  for (int64_t i = t0; i < (int64_t)I.k * I.k; i += stride) I.W[i] = KEY_NONE;
+  for (int64_t i = t0; i < (int64_t)I.k * I.k; i += stride) {
+    I.W[i] = KEY_NONE;
+    I.meta[i] = META_ALL;                       // empty center: every unit (none) held
+  }
+  for (int64_t i = t0; i < (int64_t)I.k * I.k * BEST_M; i += stride) I.best[i] = KEY_NONE;
   for (int64_t i = t0; i < I.k; i += stride) I.load[i] = 0;
   for (int64_t i = t0; i < SC_COUNT; i += stride) I.scalars[i] = 0;
 }
@@ -561,13 +653,13 @@ hipError_t launch_unpermute(int64_t n, const int64_t *order, const int32_t *assi
 }
 
 
-template <bool WLDS, int VEC>
+template <bool WLDS>
 static hipError_t launch_solve_t(const InstView &I, int64_t r_begin, int64_t r_end, size_t bytes,
                                  hipStream_t st) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&solve_kernel<WLDS, VEC>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&solve_kernel<WLDS>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
-  solve_kernel<WLDS, VEC><<<1, NT, bytes, st>>>(I, r_begin, r_end);
+  solve_kernel<WLDS><<<1, NT, bytes, st>>>(I, r_begin, r_end);
   return hipGetLastError();
 }
 
@@ -624,14 +716,8 @@ __global__ __launch_bounds__(NT) void service_kernel(ServiceCtl *ctl, const Serv
 #pragma unroll
     for (int i = 0; i < WORDS; ++i) iw[i] = __builtin_amdgcn_readfirstlane(job[i]);
     const bool wlds = solve_lds_bytes(I.k, true) <= lds_avail;
-    const bool vec = I.k % 4 == 0 && (uintptr_t)I.cm % 16 == 0;
-    if (wlds) {
-      if (vec) solve_range<true, 4>(I, 0, I.n, lds, S);
-      else solve_range<true, 1>(I, 0, I.n, lds, S);
-    } else {
-      if (vec) solve_range<false, 4>(I, 0, I.n, lds, S);
-      else solve_range<false, 1>(I, 0, I.n, lds, S);
-    }
+    if (wlds) solve_range<true>(I, 0, I.n, lds, S);
+    else solve_range<false>(I, 0, I.n, lds, S);
     __syncthreads();
     if (threadIdx.x == 0)
       __hip_atomic_store(&done[c % ring_size], c + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -693,12 +779,8 @@ hipError_t launch_solve(const InstView &I, int64_t r_begin, int64_t r_end, hipSt
   if (r_end <= r_begin) return hipSuccess;
   const bool wlds = solve_lds_bytes(I.k, true) <= LDS_BUDGET;
   const size_t bytes = solve_lds_bytes(I.k, wlds);
-  // 16-byte row loads need rows that start on 16-byte boundaries
-  const bool vec = I.k % 4 == 0 && (uintptr_t)I.cm % 16 == 0;
-  if (wlds) return vec ? launch_solve_t<true, 4>(I, r_begin, r_end, bytes, st)
-                       : launch_solve_t<true, 1>(I, r_begin, r_end, bytes, st);
-  return vec ? launch_solve_t<false, 4>(I, r_begin, r_end, bytes, st)
-             : launch_solve_t<false, 1>(I, r_begin, r_end, bytes, st);
+  return wlds ? launch_solve_t<true>(I, r_begin, r_end, bytes, st)
+              : launch_solve_t<false>(I, r_begin, r_end, bytes, st);
 }
 
 }  // namespace lbdd
