@@ -52,8 +52,8 @@ struct Lds {
   int32_t *pred;    // [k+1]
   int32_t *front0;  // [k+1] frontier lists (double-buffered) ...
   int32_t *front1;
-  int64_t *fdist0;  // [k+1] ... with the labels the nodes had when listed
-  int64_t *fdist1;
+  uint64_t *fbase0; // [k+1] ... with their packed candidate bases
+  uint64_t *fbase1;
   int64_t *pot;     // [k] node potentials (see refine)
   int32_t *load;    // [k]
   int32_t *cap;     // [k]
@@ -323,60 +323,78 @@ __device__ inline bool edge_weight(const InstView &I, const Lds &L, int s, int m
 // Bellman-Ford from node s on the split graph; leaves dist/pred in LDS.
 // Two barriers per round: relax (frontier sources -> per-target minimum),
 // then update (strict improvement, next frontier, reset of the minima).
+// A frontier entry carries its node u and the packed candidate base
+// ((label + DIST_BIAS) << 16) | u, so relaxing a transfer edge is one add of
+// delta << 16; only the key's high word (delta + 2^31, all ones = no edge) is
+// read.  s_in has no out-edges and never enters the frontier.
 // Returns false (and sets the status) on a change in round k+1.
 __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Scalars &S, int s, int mode) {
   const int k = I.k, K1 = k + 1;
   const int tid = threadIdx.x;
+  const uint32_t *Whi = reinterpret_cast<const uint32_t *>(L.W) + 1;   // high word of W[i]: Whi[2i]
   for (int v = tid; v < K1; v += NT) {
     L.dist[v] = (v == s) ? 0 : DIST_NONE;
     L.pred[v] = -1;
     L.red[v] = KEY_NONE;
   }
-  if (tid == 0) { S.nfront[0] = 1; S.nfront[1] = 0; L.front0[0] = s; L.fdist0[0] = 0; }
+  if (tid == 0) {
+    S.nfront[0] = 1;
+    S.nfront[1] = 0;
+    L.front0[0] = s;
+    L.fbase0[0] = pack_cand(0, s);
+  }
   __syncthreads();
   int cur = 0;
   for (int t = 1; t <= K1; ++t) {
     const int nf = S.nfront[cur];
     const int32_t *F = cur ? L.front1 : L.front0;
-    const int64_t *FD = cur ? L.fdist1 : L.fdist0;
+    const uint64_t *FB = cur ? L.fbase1 : L.fbase0;
+    // candidate of target v over frontier entries j = j0, j0+G, ...
+    auto relax_transfer = [&](int v, int j0, int G) -> uint64_t {
+      uint64_t best = KEY_NONE;
+      int j = j0;
+      for (; j + 3 * G < nf; j += 4 * G) {
+        uint32_t hi[4];
+        uint64_t b[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          const int u = F[j + x * G];
+          b[x] = FB[j + x * G];
+          hi[x] = Whi[2 * ((int64_t)u * k + v)];
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+          if (hi[x] != 0xffffffffu)
+            best = umin(best, b[x] + ((uint64_t)(int64_t)(int32_t)(hi[x] - 0x80000000u) << 16));
+      }
+      for (; j < nf; j += G) {
+        const uint32_t hi = Whi[2 * ((int64_t)F[j] * k + v)];
+        if (hi != 0xffffffffu)
+          best = umin(best, FB[j] + ((uint64_t)(int64_t)(int32_t)(hi - 0x80000000u) << 16));
+      }
+      return best;
+    };
+    // candidate of s_in: cycle mode W[u][s], path mode the penalty difference
+    auto relax_in = [&](int j0, int G) -> uint64_t {
+      uint64_t best = KEY_NONE;
+      for (int j = j0; j < nf; j += G) {
+        int64_t w;
+        if (edge_weight(I, L, s, mode, F[j], k, w))
+          best = umin(best, FB[j] + ((uint64_t)w << 16));
+      }
+      return best;
+    };
     if (K1 <= NT) {
       const int G = NT / K1;
       const int v = tid % K1, g = tid / K1;
-      if (g < G && v != s) {
-        uint64_t best = KEY_NONE;
-        int j = g;
-        for (; j + 3 * G < nf; j += 4 * G) {
-          int u[4];
-          int64_t du[4], w[4];
-          bool e[4];
-#pragma unroll
-          for (int x = 0; x < 4; ++x) { u[x] = F[j + x * G]; du[x] = FD[j + x * G]; }
-#pragma unroll
-          for (int x = 0; x < 4; ++x) e[x] = edge_weight(I, L, s, mode, u[x], v, w[x]);
-#pragma unroll
-          for (int x = 0; x < 4; ++x)
-            if (e[x]) best = umin(best, pack_cand(du[x] + w[x], u[x]));
-        }
-        for (; j < nf; j += G) {
-          int64_t w;
-          if (edge_weight(I, L, s, mode, F[j], v, w)) best = umin(best, pack_cand(FD[j] + w, F[j]));
-        }
-        lds_min(&L.red[v], best);
-      }
+      if (g < G && v != s) lds_min(&L.red[v], v < k ? relax_transfer(v, g, G) : relax_in(g, G));
     } else {
-      for (int v = tid; v < K1; v += NT) {
-        if (v == s) continue;
-        uint64_t best = KEY_NONE;
-        for (int j = 0; j < nf; ++j) {
-          int64_t w;
-          if (edge_weight(I, L, s, mode, F[j], v, w)) best = umin(best, pack_cand(FD[j] + w, F[j]));
-        }
-        L.red[v] = best;
-      }
+      for (int v = tid; v < K1; v += NT)
+        if (v != s) L.red[v] = v < k ? relax_transfer(v, 0, 1) : relax_in(0, 1);
     }
     __syncthreads();
     int32_t *Fn = cur ? L.front0 : L.front1;
-    int64_t *FDn = cur ? L.fdist0 : L.fdist1;
+    uint64_t *FBn = cur ? L.fbase0 : L.fbase1;
     for (int vb = 0; vb < K1; vb += NT) {
       const int v = vb + tid;
       bool ch = false;
@@ -388,7 +406,7 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
           if (d < L.dist[v]) {
             L.dist[v] = d;
             L.pred[v] = cand_node(c);
-            ch = true;
+            ch = v < k;                          // s_in has no out-edges
           }
         }
       }
@@ -400,7 +418,7 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
         base = __shfl(base, 0);
         if (ch) {
           Fn[base + lanes_below(mask)] = v;
-          FDn[base + lanes_below(mask)] = L.dist[v];
+          FBn[base + lanes_below(mask)] = pack_cand(L.dist[v], v);
         }
       }
     }
@@ -503,8 +521,8 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
   L.front0 = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
   L.front1 = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
   p = reinterpret_cast<unsigned char *>(((uintptr_t)p + 7) & ~(uintptr_t)7);
-  L.fdist0 = reinterpret_cast<int64_t *>(p); p += (size_t)K1 * 8;
-  L.fdist1 = reinterpret_cast<int64_t *>(p); p += (size_t)K1 * 8;
+  L.fbase0 = reinterpret_cast<uint64_t *>(p); p += (size_t)K1 * 8;
+  L.fbase1 = reinterpret_cast<uint64_t *>(p); p += (size_t)K1 * 8;
   L.pot = reinterpret_cast<int64_t *>(p); p += (size_t)k * 8;
   L.load = reinterpret_cast<int32_t *>(p); p += (size_t)k * 4;
   L.cap = reinterpret_cast<int32_t *>(p); p += (size_t)k * 4;

@@ -168,12 +168,6 @@ def test_invalid_cost_rejected(lb):
 
 
 # ------------------------------------------------ whole-matrix scan (a3)
-def _scan_case(k, n, seed, unallotted=0.1):
-    rng = np.random.default_rng(seed)
-    inst = L.random_small(k=k, n=n, seed=seed, cm_hi=2000) if n * k <= 5_000_000 else None
-    return inst, rng
-
-
 @pytest.mark.parametrize("k,n", [(1, 10), (8, 2000), (37, 5000), (100, 100_000), (131, 20_000)])
 def test_full_scan_bit_exact(lb, k, n):
     import torch
@@ -201,3 +195,59 @@ def test_full_scan_c3_size_bit_exact(lb):
     W = lb.best_transfers(torch.from_numpy(inst.cm).cuda(), torch.from_numpy(smin).cuda(),
                           torch.from_numpy(rank.astype(np.int32)).cuda())
     assert np.array_equal(W.cpu().numpy().view(np.uint64), ref)
+
+
+# ------------------------------------------ full-size properties (any size)
+def test_c2_zero_capacity_closed_form(lb):
+    """cap = 0 everywhere at the k=100, n=100,000 size: Equation (1) separates
+    per unit, ASRAL reaches sum_d min_s CM(d,s) + pen[s] (closed form pinned
+    against the exact optimum on small instances)."""
+    import torch
+    inst = L.make_config("C2")
+    cap = np.zeros(inst.k, np.int32)
+    say("C2 zero capacity")
+    with lb.Instance(torch.from_numpy(inst.cm).cuda(), cap, inst.pen) as I:
+        I.solve()
+        obj, a = I.objective(), I.assignment()
+    cmp = inst.cm.astype(np.int64) + inst.pen[None, :]
+    assert obj == int(cmp.min(axis=1).sum())
+    assert obj == pins.eq1(inst.cm, cap, inst.pen, a)
+
+
+def test_c2_loose_capacity_is_row_argmin(lb):
+    import torch
+    inst = L.make_config("C2")
+    cap = np.full(inst.k, inst.n, np.int32)
+    say("C2 loose capacity")
+    with lb.Instance(torch.from_numpy(inst.cm).cuda(), cap, inst.pen) as I:
+        I.solve()
+        obj, a = I.objective(), I.assignment()
+    assert np.array_equal(a, np.argmin(inst.cm, axis=1))
+    assert obj == int(inst.cm.min(axis=1).sum())
+
+
+def test_c3_prefix_bit_exact_and_invariants(lb):
+    """The k=500, n=1,000,000 workload: its first 2,000 iterations against the
+    oracle (allotment, loads, objective, whole best-transfer table), then
+    20,000 iterations checked through properties that hold at any size:
+    Equation (1), no negative cycle (Lemmas 1-2), table = its definition."""
+    import torch
+    inst = L.make_config("C3")
+    say("C3 prefix")
+    _, _, order, rank = oracle.setup(inst.cm)
+    with lb.Instance(torch.from_numpy(inst.cm).cuda(), inst.cap, inst.pen) as I:
+        I.solve_iters(2000)
+        ref = oracle.solve(*inst.arrays(), max_iters=2000, want_W=True)
+        load, W, _ = I.snapshot()
+        assert I.objective() == ref.objective
+        assert np.array_equal(I.assignment(), ref.assign)
+        assert np.array_equal(load, ref.load)
+        assert np.array_equal(W, ref.W)
+        I.solve_iters(18000)
+        a = I.assignment()
+        load, W, _ = I.snapshot()
+        assert I.progress() == 20000
+        assert I.objective() == pins.eq1(*inst.arrays(), a)
+        assert np.array_equal(np.bincount(a[a >= 0], minlength=inst.k), load)
+        assert np.array_equal(W, oracle.best_transfers(inst.cm, a, rank))
+        assert not pins.has_negative_cycle(W)
