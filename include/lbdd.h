@@ -128,7 +128,9 @@ int lbdd_snapshot(lbdd_instance *h, int32_t *load, uint64_t *W, int64_t *order);
  *   [14] device timer when the instance's first solve launch began, [15] when
  *       its last iteration so far finished (device timer ticks)
  *   [16] Bellman-Ford edge relaxations (sum over rounds of frontier x k)
- *   [17] device timer frequency in kHz
+ *   [17] path searches answered from the labels of a cycle search that ran
+ *        on the same table (part of [4])
+ *   [18] device timer frequency in kHz
  * Synchronises.  Returns the number of counters written (>= 0). */
 int lbdd_stats(lbdd_instance *h, int64_t *out, int32_t count);
 
@@ -211,12 +213,18 @@ const char *lbdd_last_error(void);
  *   cm      [n][k] int32, device      assign [n] int32 in [-1, k), device
  *   rank    [n] int32 >= 0 distinct, device (tie order of units)
  *   W       [k][k] uint64, device, written
- *   work    device scratch of at least lbdd_best_transfers_work_bytes(k, n)
- * Asynchronous on `hip_stream`.  Errors: LBDD_E_INVAL (sizes, NULL),
- * LBDD_E_DEVICE. */
+ *   work    device scratch of at least lbdd_best_transfers_work_bytes(k, n);
+ *           it holds the units grouped by center when the call returns
+ *   flags   LBDD_SCAN_REUSE_GROUPING: work already holds the grouping of this
+ *           same (assign, rank) from a previous call (e.g. after CM changed),
+ *           so only the table is cleared and the cost matrix scanned
+ * Asynchronous on `hip_stream`.  Errors: LBDD_E_INVAL (sizes, NULL, unknown
+ * flags), LBDD_E_DEVICE. */
+#define LBDD_SCAN_REUSE_GROUPING 0x1u
 size_t lbdd_best_transfers_work_bytes(int32_t k, int64_t n);
 int lbdd_best_transfers(int32_t k, int64_t n, const int32_t *cm, const int32_t *assign,
-                        const int32_t *rank, uint64_t *W, void *work, void *hip_stream);
+                        const int32_t *rank, uint64_t *W, void *work, uint32_t flags,
+                        void *hip_stream);
 
 #ifdef __cplusplus
 }

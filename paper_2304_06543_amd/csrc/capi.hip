@@ -56,7 +56,7 @@ void release(lbdd_instance *h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->st);
   void *ptrs[] = {h->cm, h->smin, h->cap, h->pen, h->assign, h->load, h->members,
-                  h->slot, h->unperm, h->order, h->scalars, h->W, h->best, h->meta};
+                  h->slot, h->unperm, h->order, h->scalars, h->W, h->best, h->meta, h->thr};
   for (void *p : ptrs)
     if (p) (void)hipFreeAsync(p, h->st);
   (void)hipStreamSynchronize(h->st);
@@ -132,6 +132,7 @@ int lbdd_create(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity
   if (e == hipSuccess) e = dalloc(&h->W, (size_t)k * k, h->st);
   if (e == hipSuccess) e = dalloc(&h->best, (size_t)k * k * lbdd::BEST_M, h->st);
   if (e == hipSuccess) e = dalloc(&h->meta, (size_t)k * k, h->st);
+  if (e == hipSuccess) e = dalloc(&h->thr, (size_t)k * k, h->st);
   if (e != hipSuccess) { release(h); return hip_fail(e, "device allocation"); }
 
   // setup scratch: the unpermuted CM (host input only), sort keys, a flag
@@ -315,12 +316,15 @@ size_t lbdd_best_transfers_work_bytes(int32_t k, int64_t n) {
 }
 
 int lbdd_best_transfers(int32_t k, int64_t n, const int32_t *cm, const int32_t *assign,
-                        const int32_t *rank, uint64_t *W, void *work, void *hip_stream) {
+                        const int32_t *rank, uint64_t *W, void *work, uint32_t flags,
+                        void *hip_stream) {
   g_err.clear();
   if (k < 1 || k > LBDD_MAX_K) return fail(LBDD_E_INVAL, "k=%d outside [1, %d]", k, LBDD_MAX_K);
   if (n < 0 || n > LBDD_MAX_N) return fail(LBDD_E_INVAL, "n=%lld outside [0, 2^31-1]", (long long)n);
   if (!W || !work || (n > 0 && (!cm || !assign || !rank))) return fail(LBDD_E_INVAL, "NULL argument");
-  HIP_TRY(lbdd::launch_full_scan(k, n, cm, assign, rank, W, work, static_cast<hipStream_t>(hip_stream)),
+  if (flags & ~LBDD_SCAN_REUSE_GROUPING) return fail(LBDD_E_INVAL, "unknown flags 0x%x", flags);
+  HIP_TRY(lbdd::launch_full_scan(k, n, cm, assign, rank, W, work, flags & LBDD_SCAN_REUSE_GROUPING,
+                                 static_cast<hipStream_t>(hip_stream)),
           "scan kernels");
   return LBDD_OK;
 }

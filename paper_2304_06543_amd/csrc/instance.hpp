@@ -27,12 +27,13 @@ struct lbdd_instance {
   uint64_t *W = nullptr;
   uint64_t *best = nullptr;
   uint8_t *meta = nullptr;
+  uint64_t *thr = nullptr;
 
   lbdd::InstView view() const {
     lbdd::InstView v;
     v.k = k; v.n = n; v.cm = cm; v.smin = smin; v.cap = cap; v.pen = pen;
     v.assign = assign; v.load = load; v.members = members; v.slot = slot; v.W = W;
-    v.best = best; v.meta = meta;
+    v.best = best; v.meta = meta; v.thr = thr;
     v.scalars = scalars;
     return v;
   }

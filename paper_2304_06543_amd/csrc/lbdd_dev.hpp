@@ -51,6 +51,8 @@ struct InstView {
   uint64_t *W;             // [k][k] best-transfer table (heads of the lists below)
   uint64_t *best;          // [k][k][BEST_M] smallest transfer keys of each pair
   uint8_t *meta;           // [k][k] keys held (low 4 bits), every unit held (META_ALL)
+  uint64_t *thr;           // [k][k] a joining unit's key changes the list (or its
+                           // flags) only if it is below this threshold
   int64_t *scalars;        // [SC_COUNT] objective, progress, status, counters
 };
 
@@ -66,7 +68,7 @@ enum : int {
   SC_DONE = 1,          // iterations completed
   SC_STATUS = 2,        // 0 ok, else an LBDD_E_* code
   SC_STAT0 = 3,         // first of the counters reported by lbdd_stats
-  SC_NSTATS = 17,
+  SC_NSTATS = 18,
   SC_COUNT = SC_STAT0 + SC_NSTATS
 };
 enum : int {
@@ -77,7 +79,8 @@ enum : int {
   ST_REFILLS,           // list refills (column rescans)
   ST_T_FIRST,           // device timer when the instance's first launch began
   ST_T_LAST,            // device timer when its last iteration finished
-  ST_RELAX              // Bellman-Ford edge relaxations (frontier size x targets)
+  ST_RELAX,             // Bellman-Ford edge relaxations (frontier size x targets)
+  ST_PATH_DERIVED       // path searches answered from the cycle search's labels
 };
 
 // one workgroup solves one instance
@@ -124,6 +127,7 @@ hipError_t launch_service(ServiceCtl *ctl, const ServiceJob *ring, int32_t ring_
 // scan.hip: whole-matrix best-transfer table
 size_t scan_work_bytes(int32_t k, int64_t n);
 hipError_t launch_full_scan(int32_t k, int64_t n, const int32_t *cm, const int32_t *assign,
-                            const int32_t *rank, uint64_t *W, void *work, hipStream_t st);
+                            const int32_t *rank, uint64_t *W, void *work, bool reuse_grouping,
+                            hipStream_t st);
 
 }  // namespace lbdd

@@ -289,22 +289,26 @@ size_t scan_work_bytes(int32_t k, int64_t n) {
 }
 
 hipError_t launch_full_scan(int32_t k, int64_t n, const int32_t *cm, const int32_t *assign,
-                            const int32_t *rank, uint64_t *W, void *work, hipStream_t st) {
+                            const int32_t *rank, uint64_t *W, void *work, bool reuse_grouping,
+                            hipStream_t st) {
   ScanWork w = carve(work, k);
   hipError_t e;
-  fill_kernel<<<256, 256, 0, st>>>((int64_t)k * k, KEY_NONE, W, k, w.count, w.cursor);
+  // the counts are cleared too, unless the grouping of a previous call is reused
+  fill_kernel<<<256, 256, 0, st>>>((int64_t)k * k, KEY_NONE, W, reuse_grouping ? 0 : k, w.count, w.cursor);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (n == 0) return hipSuccess;
-  int64_t hb = (n + 1023) / 1024;
-  if (hb > 2048) hb = 2048;
-  histogram_kernel<<<(unsigned)hb, 1024, (size_t)k * 4, st>>>(k, n, assign, w.count);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  offsets_kernel<<<1, 1024, 0, st>>>(k, w.count, w.offset);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int64_t per_block = (int64_t)SCATTER_THREADS * SCATTER_ITEMS;
-  scatter_kernel<<<(unsigned)((n + per_block - 1) / per_block), SCATTER_THREADS, (size_t)k * 8, st>>>(
-      k, n, assign, rank, w.offset, w.cursor, w.units);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (!reuse_grouping) {   // group the units by center
+    int64_t hb = (n + 1023) / 1024;
+    if (hb > 2048) hb = 2048;
+    histogram_kernel<<<(unsigned)hb, 1024, (size_t)k * 4, st>>>(k, n, assign, w.count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    offsets_kernel<<<1, 1024, 0, st>>>(k, w.count, w.offset);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t per_block = (int64_t)SCATTER_THREADS * SCATTER_ITEMS;
+    scatter_kernel<<<(unsigned)((n + per_block - 1) / per_block), SCATTER_THREADS, (size_t)k * 8, st>>>(
+        k, n, assign, rank, w.offset, w.cursor, w.units);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   int dev = 0, cus = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;

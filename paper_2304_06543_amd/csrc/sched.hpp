@@ -74,7 +74,7 @@ struct AdmissionQueue {
 // unpermuted cost matrix copy and sort keys).
 inline size_t instance_footprint(int32_t k, int64_t n) {
   const size_t nk = (size_t)n * (size_t)k;
-  return nk * 4 * 3 + (size_t)n * (4 * 4 + 8 + 4 + 16) + (size_t)k * k * (8 + 8 * 8 + 1) +
+  return nk * 4 * 3 + (size_t)n * (4 * 4 + 8 + 4 + 16) + (size_t)k * k * (8 + 8 * 8 + 1 + 8) +
          (size_t)k * 16 + 4096;
 }
 

@@ -50,6 +50,7 @@ struct Lds {
   uint64_t *red;    // [k+1] per-target minimum
   int64_t *dist;    // [k+1]
   int32_t *pred;    // [k+1]
+  int32_t *hop;     // [k+1] round in which the label last changed (0 for s)
   int32_t *front0;  // [k+1] frontier lists (double-buffered) ...
   int32_t *front1;
   uint64_t *fbase0; // [k+1] ... with their packed candidate bases
@@ -82,7 +83,7 @@ struct Scalars {
 // without the k x k table in LDS.
 __host__ __device__ size_t solve_lds_bytes(int k, bool wlds) {
   const size_t K1 = (size_t)k + 1;
-  size_t b = K1 * 8 * 2 + K1 * 4 * 3 + 8 + K1 * 8 * 2 + (size_t)k * 8 + (size_t)k * 4 * 3 +
+  size_t b = K1 * 8 * 2 + K1 * 4 * 4 + 8 + K1 * 8 * 2 + (size_t)k * 8 + (size_t)k * 4 * 3 +
              K1 * 4 * 3 + K1 * 4 + 8 + 2 * (SOLVE_THREADS / 64) * 8;
   if (wlds) b += (size_t)k * k * 8;
   return b;
@@ -129,6 +130,17 @@ __device__ inline void list_merge(uint64_t (&a)[BEST_M], uint64_t q) {
   }
 }
 
+// Threshold below which a joining key touches the list: while every unit is
+// held and there is room, always; otherwise only in front of the last held
+// key (an unknown list takes nothing: threshold 0).
+__device__ inline uint64_t list_threshold(const uint64_t (&a)[BEST_M], int c, bool all) {
+  if (all) return KEY_NONE;                      // enters, or clears the all-held flag
+  uint64_t t = 0;
+#pragma unroll
+  for (int i = 0; i < BEST_M; ++i) t = (i == c - 1) ? a[i] : t;
+  return t;
+}
+
 // Unit x (row x) joins center v: its keys enter v's lists, row v of W follows.
 // Returns (block-wide) bit 0: some W entry decreased; bit 1: a decreased entry
 // breaks the node potentials.
@@ -142,21 +154,21 @@ __device__ __forceinline__ int join_center(const InstView &I, const Lds &L, int 
     const int32_t delta = rx[w] - base;
     const uint64_t q = pack_key(delta, (uint32_t)x);
     const int64_t idx = (int64_t)v * k + w;
+    // with every unit held q always enters; otherwise only in front of a held
+    // key (beyond the last held key an unheld unit may be smaller)
+    if (!(q < I.thr[idx])) continue;
     const uint8_t meta = I.meta[idx];
     const int c = meta & 15;
     const bool all = meta & META_ALL;
     uint64_t a[BEST_M];
     list_load(I.best + idx * BEST_M, a);
-    int below = 0;                                // held keys smaller than q
-#pragma unroll
-    for (int i = 0; i < BEST_M; ++i) below += a[i] < q;
-    // with every unit held q always enters; otherwise only in front of a held
-    // key (beyond the last held key an unheld unit may be smaller)
-    if (!(all || below < c)) continue;
     list_merge(a, q);
     list_store(I.best + idx * BEST_M, a);
     const bool full = c == BEST_M;
-    I.meta[idx] = (uint8_t)((full ? BEST_M : c + 1) | (all && !full ? META_ALL : 0));
+    const int c2 = full ? BEST_M : c + 1;
+    const bool all2 = all && !full;
+    I.meta[idx] = (uint8_t)(c2 | (all2 ? META_ALL : 0));
+    I.thr[idx] = list_threshold(a, c2, all2);
     if (a[0] < L.W[idx]) {
       L.W[idx] = a[0];
       changed = 1;
@@ -191,6 +203,7 @@ __device__ __forceinline__ void leave_center(const InstView &I, const Lds &L, in
     a[BEST_M - 1] = KEY_NONE;
     list_store(I.best + idx * BEST_M, a);
     I.meta[idx] = (uint8_t)((c - 1) | (meta & META_ALL));
+    I.thr[idx] = list_threshold(a, c - 1, meta & META_ALL);
     L.W[idx] = a[0];                             // stale if unknown; refill sets it
   }
   __syncthreads();
@@ -252,6 +265,7 @@ __device__ __forceinline__ void refill_column(const InstView &I, const Lds &L, S
 #pragma unroll
     for (int j = 0; j < BEST_M; ++j) c += out[j] != KEY_NONE;
     I.meta[idx] = (uint8_t)(c | (m <= BEST_M ? META_ALL : 0));
+    I.thr[idx] = list_threshold(out, c, m <= BEST_M);
     L.W[idx] = out[0];
     S.stats[ST_ROWS_SCANNED] += m;
     S.stats[ST_REFILLS] += 1;
@@ -335,6 +349,7 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
   for (int v = tid; v < K1; v += NT) {
     L.dist[v] = (v == s) ? 0 : DIST_NONE;
     L.pred[v] = -1;
+    L.hop[v] = (v == s) ? 0 : -1;
     L.red[v] = KEY_NONE;
   }
   if (tid == 0) {
@@ -406,6 +421,7 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
           if (d < L.dist[v]) {
             L.dist[v] = d;
             L.pred[v] = cand_node(c);
+            L.hop[v] = t;
             ch = v < k;                          // s_in has no out-edges
           }
         }
@@ -437,17 +453,62 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
   return false;
 }
 
+// Path search result from the labels a cycle search left on the same W
+// (it applied nothing, so the transfer graph is unchanged).  Both searches
+// relax the same transfer edges and s_in has no out-edges, so every center's
+// label and predecessor are the same; only s_in differs.  In synchronous
+// rounds s_in first reaches its final label best = min_u dist[u] + pe(u) in
+// the round after the earliest of those minimisers got its final label
+// (hop[u]), and its predecessor is the smallest minimiser with that hop.
+__device__ __forceinline__ void path_from_labels(const InstView &I, const Lds &L, Scalars &S, int s) {
+  const int k = I.k;
+  const int tid = threadIdx.x;
+  if (tid == 0) { L.red[0] = KEY_NONE; L.red[1] = KEY_NONE; }
+  __syncthreads();
+  for (int u = tid; u < k; u += NT) {
+    if (u == s || L.dist[u] == DIST_NONE) continue;
+    const int64_t c = L.dist[u] + (L.load[u] >= L.cap[u] ? L.pen[u] : 0) - L.pen[s];
+    atomicMin((unsigned long long *)&L.red[0], (unsigned long long)(c + DIST_BIAS));
+  }
+  __syncthreads();
+  const uint64_t best = L.red[0];
+  for (int u = tid; u < k; u += NT) {
+    if (u == s || L.dist[u] == DIST_NONE || best == KEY_NONE) continue;
+    const int64_t c = L.dist[u] + (L.load[u] >= L.cap[u] ? L.pen[u] : 0) - L.pen[s];
+    if ((uint64_t)(c + DIST_BIAS) == best)
+      atomicMin((unsigned long long *)&L.red[1], (unsigned long long)((uint64_t)L.hop[u] << 32 | (uint32_t)u));
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (best == KEY_NONE) {
+      L.dist[k] = DIST_NONE;
+      L.pred[k] = -1;
+    } else {
+      L.dist[k] = (int64_t)best - DIST_BIAS;
+      L.pred[k] = (int32_t)(uint32_t)L.red[1];
+    }
+    S.stats[ST_PATH_DERIVED] += 1;
+  }
+  __syncthreads();
+}
+
 // One refinement (mode 0: Algorithm 1, mode 1: Appendix A) anchored at s.
+// With have_labels (mode 1 only) the search result is derived from the labels
+// of the cycle search just run on the same W.  Returns true when nothing was
+// applied and the search succeeded: the labels in LDS then describe the
+// current W.
 template <bool WLDS>
-__device__ __forceinline__ void refine(const InstView &I, const Lds &L, Scalars &S, int s, int mode) {
+__device__ __forceinline__ bool refine(const InstView &I, const Lds &L, Scalars &S, int s, int mode,
+                                       bool have_labels) {
   const int k = I.k;
   const int tid = threadIdx.x;
   if (tid == 0) S.stats[mode == 0 ? ST_CYC_SEARCH : ST_PATH_SEARCH] += 1;
-  if (!bellman_ford(I, L, S, s, mode)) return;
+  if (have_labels) path_from_labels(I, L, S, s);
+  else if (!bellman_ford(I, L, S, s, mode)) return false;
   const int64_t D = L.dist[k];
   if (D == DIST_NONE || D >= 0) {             // only strictly negative refinements apply
-    adopt_potential(I, L, S, s);
-    return;
+    if (!have_labels) adopt_potential(I, L, S, s);
+    return true;
   }
   if (tid == 0) {
     S.pot_ok = 0;                             // W is about to change
@@ -495,7 +556,7 @@ __device__ __forceinline__ void refine(const InstView &I, const Lds &L, Scalars 
   }
   __syncthreads();
   const int nmov = S.nmoves;
-  const int64_t t0 = now();
+  const int64_t t0 = tid == 0 ? now() : 0;
   // every unit leaves its old center's lists before any joins the new ones;
   // lists left unknown are refilled from the final members
   for (int e = 0; e < nmov; ++e) leave_center(I, L, L.mrow[e], L.mfrom[e]);
@@ -503,6 +564,7 @@ __device__ __forceinline__ void refine(const InstView &I, const Lds &L, Scalars 
   for (int e = 0; e < nmov; ++e) refill_center(I, L, S, L.mfrom[e]);
   if (tid == 0) S.stats[ST_T_RESCAN] += now() - t0;
   __syncthreads();
+  return false;
 }
 
 // Iterations [r_begin, r_end) of one instance by the calling workgroup.
@@ -518,9 +580,10 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
   L.red = reinterpret_cast<uint64_t *>(p); p += (size_t)K1 * 8;
   L.dist = reinterpret_cast<int64_t *>(p); p += (size_t)K1 * 8;
   L.pred = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
+  L.hop = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
   L.front0 = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
   L.front1 = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
-  p = reinterpret_cast<unsigned char *>(((uintptr_t)p + 7) & ~(uintptr_t)7);
+  p = lds + (((p - lds) + 7) & ~(ptrdiff_t)7);   // offsets keep the LDS address space
   L.fbase0 = reinterpret_cast<uint64_t *>(p); p += (size_t)K1 * 8;
   L.fbase1 = reinterpret_cast<uint64_t *>(p); p += (size_t)K1 * 8;
   L.pot = reinterpret_cast<int64_t *>(p); p += (size_t)k * 8;
@@ -531,7 +594,7 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
   L.mfrom = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
   L.mto = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
   L.trow = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
-  p = reinterpret_cast<unsigned char *>(((uintptr_t)p + 7) & ~(uintptr_t)7);
+  p = lds + (((p - lds) + 7) & ~(ptrdiff_t)7);   // offsets keep the LDS address space
   L.wmin = reinterpret_cast<uint64_t *>(p);
 
   if (WLDS)
@@ -552,7 +615,7 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
   int64_t r = r_begin;
   if (ok0) {
     for (; r < r_end; ++r) {
-      const int64_t t0 = now();
+      const int64_t t0 = tid == 0 ? now() : 0;   // phase timers: thread 0 only
       const int s = I.smin[r];
       const int32_t *row = I.cm + r * k;
       if (tid == 0) {
@@ -566,17 +629,18 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
         S.obj += (int64_t)row[s] + (vac ? 0 : L.pen[s]);
       }
       const int ins = join_center(I, L, (int)r, s);   // contains barriers
-      const int64_t t1 = now();
+      const int64_t t1 = tid == 0 ? now() : 0;
       // Negative Cycle Refinement can only find something if the current W
       // may hold a negative cycle: the insert lowered an entry and the node
       // potentials no longer certify that W has none.
       const bool search = (ins & 1) && (!S.pot_ok || (ins & 2));
-      if (search) refine<WLDS>(I, L, S, s, 0);
+      bool labels = false;                        // LDS labels describe the current W
+      if (search) labels = refine<WLDS>(I, L, S, s, 0, false);
       else if (tid == 0) S.stats[ST_CYC_SKIPPED] += 1;
       __syncthreads();
-      const int64_t t2 = now();
+      const int64_t t2 = tid == 0 ? now() : 0;
       if (S.status != 0) break;
-      if (!S.vacant) refine<WLDS>(I, L, S, s, 1);
+      if (!S.vacant) refine<WLDS>(I, L, S, s, 1, labels && S.status == 0);
       __syncthreads();
       if (tid == 0) {
         const int64_t t3 = now();
@@ -644,6 +708,7 @@ __global__ void init_state_kernel(InstView I) {
   for (int64_t i = t0; i < (int64_t)I.k * I.k; i += stride) {
     I.W[i] = KEY_NONE;
     I.meta[i] = META_ALL;                       // empty center: every unit (none) held
+    I.thr[i] = KEY_NONE;                        // ... so every joining unit enters
   }
   for (int64_t i = t0; i < (int64_t)I.k * I.k * BEST_M; i += stride) I.best[i] = KEY_NONE;
   for (int64_t i = t0; i < I.k; i += stride) I.load[i] = 0;

@@ -25,7 +25,7 @@ MAX_K = 2048
 STATS = ("cycles", "paths", "moves", "cycle_searches", "path_searches", "bf_rounds",
          "rows_scanned", "iterations", "cycle_searches_skipped",
          "ticks_allot", "ticks_cycle", "ticks_path", "ticks_rescan", "refills",
-         "tick_first", "tick_last", "relaxations", "timer_khz")
+         "tick_first", "tick_last", "relaxations", "paths_derived", "timer_khz")
 
 # every symbol include/lbdd.h declares
 EXPORTS = ("lbdd_create", "lbdd_solve", "lbdd_solve_iters", "lbdd_solve_batch", "lbdd_objective",
@@ -69,7 +69,7 @@ def load(path: str = LIB_PATH):
         "lbdd_destroy": ([P], None),
         "lbdd_last_error": ([], C.c_char_p),
         "lbdd_best_transfers_work_bytes": ([I32, I64], C.c_size_t),
-        "lbdd_best_transfers": ([I32, I64, P, P, P, P, P, P], C.c_int),
+        "lbdd_best_transfers": ([I32, I64, P, P, P, P, P, U32, P], C.c_int),
         "lbdd_server_create": ([C.c_size_t, I32, I32, C.POINTER(P)], C.c_int),
         "lbdd_server_submit": ([P, I32, I64, P, P, P, C.POINTER(C.c_uint64)], C.c_int),
         "lbdd_server_poll": ([P, C.c_uint64, C.POINTER(I32), C.POINTER(I64)], C.c_int),
@@ -217,11 +217,16 @@ def best_transfers_work_bytes(k: int, n: int) -> int:
     return int(load().lbdd_best_transfers_work_bytes(int(k), int(n)))
 
 
-def best_transfers(cm, assign, rank, W=None, work=None, stream=None):
+SCAN_REUSE_GROUPING = 0x1
+
+
+def best_transfers(cm, assign, rank, W=None, work=None, stream=None, reuse_grouping=False):
     """Best-transfer table of an allotment over the whole cost matrix.
 
     cm [n][k] int32, assign [n] int32, rank [n] int32: torch cuda tensors.
-    Returns W as a torch int64 tensor [k][k] holding the uint64 key bits."""
+    Returns W as a torch int64 tensor [k][k] holding the uint64 key bits.
+    reuse_grouping: `work` holds the grouping of the same assign/rank from a
+    previous call; only the scan runs."""
     import torch
     n, k = cm.shape
     for t in (cm, assign, rank):
@@ -234,6 +239,7 @@ def best_transfers(cm, assign, rank, W=None, work=None, stream=None):
     _check(load().lbdd_best_transfers(int(k), int(n), C.c_void_p(cm.data_ptr()),
                                       C.c_void_p(assign.data_ptr()), C.c_void_p(rank.data_ptr()),
                                       C.c_void_p(W.data_ptr()), C.c_void_p(work.data_ptr()),
+                                      SCAN_REUSE_GROUPING if reuse_grouping else 0,
                                       _stream_ptr(stream)))
     return W
 

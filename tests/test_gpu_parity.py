@@ -177,10 +177,16 @@ def test_full_scan_bit_exact(lb, k, n):
     rank = rng.permutation(n).astype(np.int32)
     say("scan", k, n)
     ref = oracle.best_transfers(cm, assign, rank.astype(np.int64))
-    W = lb.best_transfers(torch.from_numpy(cm).cuda(), torch.from_numpy(assign).cuda(),
-                          torch.from_numpy(rank).cuda())
-    got = W.cpu().numpy().view(np.uint64)
-    assert np.array_equal(got, ref)
+    cmd = torch.from_numpy(cm).cuda()
+    ad, rd = torch.from_numpy(assign).cuda(), torch.from_numpy(rank).cuda()
+    work = torch.empty(lb.best_transfers_work_bytes(k, n), dtype=torch.uint8, device="cuda")
+    W = lb.best_transfers(cmd, ad, rd, work=work)
+    assert np.array_equal(W.cpu().numpy().view(np.uint64), ref)
+    # a second scan of changed costs reusing the grouping of the same allotment
+    cm2 = (cm[:, ::-1] + 7).copy()
+    ref2 = oracle.best_transfers(cm2, assign, rank.astype(np.int64))
+    W2 = lb.best_transfers(torch.from_numpy(cm2).cuda(), ad, rd, work=work, reuse_grouping=True)
+    assert np.array_equal(W2.cpu().numpy().view(np.uint64), ref2)
 
 
 def test_full_scan_c3_size_bit_exact(lb):
