@@ -130,7 +130,11 @@ int lbdd_snapshot(lbdd_instance *h, int32_t *load, uint64_t *W, int64_t *order);
  *   [16] Bellman-Ford edge relaxations (sum over rounds of frontier x k)
  *   [17] path searches answered from the labels of a cycle search that ran
  *        on the same table (part of [4])
- *   [18] device timer frequency in kHz
+ *   [18] searches run in Dijkstra order on feasible node potentials (part
+ *        of [3] + [4]; the others run as Bellman-Ford rounds or are [17])
+ *   [19] applied refinements after which the search labels were still
+ *        feasible node potentials of the changed table
+ *   [20] device timer frequency in kHz
  * Synchronises.  Returns the number of counters written (>= 0). */
 int lbdd_stats(lbdd_instance *h, int64_t *out, int32_t count);
 

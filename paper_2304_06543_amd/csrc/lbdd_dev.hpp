@@ -68,7 +68,7 @@ enum : int {
   SC_DONE = 1,          // iterations completed
   SC_STATUS = 2,        // 0 ok, else an LBDD_E_* code
   SC_STAT0 = 3,         // first of the counters reported by lbdd_stats
-  SC_NSTATS = 18,
+  SC_NSTATS = 20,
   SC_COUNT = SC_STAT0 + SC_NSTATS
 };
 enum : int {
@@ -80,7 +80,9 @@ enum : int {
   ST_T_FIRST,           // device timer when the instance's first launch began
   ST_T_LAST,            // device timer when its last iteration finished
   ST_RELAX,             // Bellman-Ford edge relaxations (frontier size x targets)
-  ST_PATH_DERIVED       // path searches answered from the cycle search's labels
+  ST_PATH_DERIVED,      // path searches answered from the cycle search's labels
+  ST_DIJKSTRA,          // searches run in Dijkstra order on feasible potentials
+  ST_POT_KEPT           // applied refinements whose labels stayed feasible potentials
 };
 
 // one workgroup solves one instance

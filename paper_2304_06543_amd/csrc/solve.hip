@@ -75,6 +75,8 @@ struct Scalars {
   int32_t nrefill;
   int32_t pot_ok;   // pot is feasible for the current W
   int32_t vacant;
+  int32_t depth;    // running mean of (deepest hop + 1) of recent searches, x16
+  int32_t maxhop;   // deepest hop of the last search in Dijkstra order
 };
 
 }  // namespace
@@ -311,42 +313,50 @@ __device__ __forceinline__ void adopt_potential(const InstView &I, const Lds &L,
   __syncthreads();
 }
 
-// Weight of edge u -> v on the split graph (node s = s_out, node k = s_in);
-// returns false when the edge does not exist.
-__device__ inline bool edge_weight(const InstView &I, const Lds &L, int s, int mode, int u, int v,
-                                   int64_t &w) {
+// After a refinement has been applied, its labels (shortest distances from s
+// on the table before the moves) are tried as the node potentials of the new
+// table.  The moves change only the rows of the centers they move units
+// between, and the labels satisfy every other edge except those into s (the
+// search never enters s), so checking those rows and column s decides
+// feasibility exactly.
+__device__ __forceinline__ void retry_potential(const InstView &I, const Lds &L, Scalars &S, int s,
+                                                int nmov) {
   const int k = I.k;
-  if (u == k || v == s || u == v) return false;
-  if (v == k) {
-    if (u == s) return false;
-    if (mode == 0) {
-      const uint64_t key = L.W[(int64_t)u * k + s];
-      if (key == KEY_NONE) return false;
-      w = key_delta(key);
-    } else {
-      w = (int64_t)(L.load[u] >= L.cap[u] ? L.pen[u] : 0) - L.pen[s];
-    }
-    return true;
+  int bad = 0;
+  for (int u = threadIdx.x; u < k; u += NT) bad |= L.dist[u] == DIST_NONE;
+  const int nrows = 2 * nmov + 1;                // from/to of every move, then column s
+  for (int64_t t = threadIdx.x; t < (int64_t)nrows * k; t += NT) {
+    const int j = (int)(t / k), w = (int)(t - (int64_t)j * k);
+    const int u = j < 2 * nmov ? ((j & 1) ? L.mto[j >> 1] : L.mfrom[j >> 1]) : w;
+    const int v = j < 2 * nmov ? w : s;
+    if (u == v || L.dist[u] == DIST_NONE || L.dist[v] == DIST_NONE) continue;
+    const uint64_t key = L.W[(int64_t)u * k + v];
+    if (key != KEY_NONE && L.dist[u] + key_delta(key) < L.dist[v]) bad = 1;
   }
-  const uint64_t key = L.W[(int64_t)u * k + v];
-  if (key == KEY_NONE) return false;
-  w = key_delta(key);
-  return true;
+  bad = __syncthreads_or(bad);
+  if (!bad)
+    for (int u = threadIdx.x; u < k; u += NT) L.pot[u] = L.dist[u];
+  if (threadIdx.x == 0) {
+    S.pot_ok = !bad;
+    if (!bad) S.stats[ST_POT_KEPT] += 1;
+  }
+  __syncthreads();
 }
 
-// Bellman-Ford from node s on the split graph; leaves dist/pred in LDS.
-// Two barriers per round: relax (frontier sources -> per-target minimum),
-// then update (strict improvement, next frontier, reset of the minima).
-// A frontier entry carries its node u and the packed candidate base
+// Bellman-Ford from node s over the centers of the split graph; leaves the
+// center labels dist/pred/hop in LDS (s_in follows with sin_from_labels: it
+// has no out-edges, so it never changes a center's label).  Two barriers per
+// round: relax (frontier sources -> per-target minimum), then update (strict
+// improvement, next frontier, reset of the minima).  A frontier entry holds
+// the row offset u*k of its center and the packed candidate base
 // ((label + DIST_BIAS) << 16) | u, so relaxing a transfer edge is one add of
 // delta << 16; only the key's high word (delta + 2^31, all ones = no edge) is
-// read.  s_in has no out-edges and never enters the frontier.
-// Returns false (and sets the status) on a change in round k+1.
-__device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Scalars &S, int s, int mode) {
-  const int k = I.k, K1 = k + 1;
+// read.  Returns false (and sets the status) on a change in round k+1.
+__device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Scalars &S, int s) {
+  const int k = I.k;
   const int tid = threadIdx.x;
   const uint32_t *Whi = reinterpret_cast<const uint32_t *>(L.W) + 1;   // high word of W[i]: Whi[2i]
-  for (int v = tid; v < K1; v += NT) {
+  for (int v = tid; v <= k; v += NT) {
     L.dist[v] = (v == s) ? 0 : DIST_NONE;
     L.pred[v] = -1;
     L.hop[v] = (v == s) ? 0 : -1;
@@ -355,65 +365,60 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
   if (tid == 0) {
     S.nfront[0] = 1;
     S.nfront[1] = 0;
-    L.front0[0] = s;
+    L.front0[0] = s * k;
     L.fbase0[0] = pack_cand(0, s);
   }
   __syncthreads();
+  // target v of this thread and its share g of the frontier (k <= NT: every
+  // target gets G = NT / k threads)
+  const int G = k <= NT ? NT / k : 1;
+  const int tv = k <= NT ? tid % k : tid;
+  const int tg = k <= NT ? tid / k : 0;
+  int64_t rounds = 0, relax = 0;
   int cur = 0;
-  for (int t = 1; t <= K1; ++t) {
+  bool conv = false;
+  for (int t = 1; t <= k + 1; ++t) {
     const int nf = S.nfront[cur];
     const int32_t *F = cur ? L.front1 : L.front0;
     const uint64_t *FB = cur ? L.fbase1 : L.fbase0;
-    // candidate of target v over frontier entries j = j0, j0+G, ...
-    auto relax_transfer = [&](int v, int j0, int G) -> uint64_t {
+    // candidate of target v over frontier entries j = j0, j0+G, ... in
+    // batches of four: all loads of a batch are in flight together
+    auto relax_target = [&](int v, int j0) -> uint64_t {
       uint64_t best = KEY_NONE;
-      int j = j0;
-      for (; j + 3 * G < nf; j += 4 * G) {
-        uint32_t hi[4];
+      for (int j = j0; j < nf; j += 4 * G) {
+        int32_t off[4];
         uint64_t b[4];
+        bool ok[4];
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
-          const int u = F[j + x * G];
-          b[x] = FB[j + x * G];
-          hi[x] = Whi[2 * ((int64_t)u * k + v)];
+          const int jj = j + x * G;
+          ok[x] = jj < nf;
+          off[x] = F[ok[x] ? jj : j];
+          b[x] = FB[ok[x] ? jj : j];
         }
+        uint32_t hi[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) hi[x] = Whi[2 * ((int64_t)off[x] + v)];
 #pragma unroll
         for (int x = 0; x < 4; ++x)
-          if (hi[x] != 0xffffffffu)
+          if (ok[x] && hi[x] != 0xffffffffu)
             best = umin(best, b[x] + ((uint64_t)(int64_t)(int32_t)(hi[x] - 0x80000000u) << 16));
       }
-      for (; j < nf; j += G) {
-        const uint32_t hi = Whi[2 * ((int64_t)F[j] * k + v)];
-        if (hi != 0xffffffffu)
-          best = umin(best, FB[j] + ((uint64_t)(int64_t)(int32_t)(hi - 0x80000000u) << 16));
-      }
       return best;
     };
-    // candidate of s_in: cycle mode W[u][s], path mode the penalty difference
-    auto relax_in = [&](int j0, int G) -> uint64_t {
-      uint64_t best = KEY_NONE;
-      for (int j = j0; j < nf; j += G) {
-        int64_t w;
-        if (edge_weight(I, L, s, mode, F[j], k, w))
-          best = umin(best, FB[j] + ((uint64_t)w << 16));
-      }
-      return best;
-    };
-    if (K1 <= NT) {
-      const int G = NT / K1;
-      const int v = tid % K1, g = tid / K1;
-      if (g < G && v != s) lds_min(&L.red[v], v < k ? relax_transfer(v, g, G) : relax_in(g, G));
+    if (k <= NT) {
+      if (tg < G && tv != s) lds_min(&L.red[tv], relax_target(tv, tg));
     } else {
-      for (int v = tid; v < K1; v += NT)
-        if (v != s) L.red[v] = v < k ? relax_transfer(v, 0, 1) : relax_in(0, 1);
+      for (int v = tid; v < k; v += NT)
+        if (v != s) L.red[v] = relax_target(v, 0);
     }
     __syncthreads();
     int32_t *Fn = cur ? L.front0 : L.front1;
     uint64_t *FBn = cur ? L.fbase0 : L.fbase1;
-    for (int vb = 0; vb < K1; vb += NT) {
+    for (int vb = 0; vb < k; vb += NT) {
       const int v = vb + tid;
       bool ch = false;
-      if (v < K1) {
+      if (v < k) {
         const uint64_t c = L.red[v];
         if (c != KEY_NONE) {
           L.red[v] = KEY_NONE;
@@ -422,7 +427,7 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
             L.dist[v] = d;
             L.pred[v] = cand_node(c);
             L.hop[v] = t;
-            ch = v < k;                          // s_in has no out-edges
+            ch = true;
           }
         }
       }
@@ -431,51 +436,64 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
       if (mask) {
         int base = 0;
         if ((tid & 63) == 0) base = atomicAdd(&S.nfront[cur ^ 1], __popcll(mask));
-        base = __shfl(base, 0);
+        base = __builtin_amdgcn_readlane(base, 0);
         if (ch) {
-          Fn[base + lanes_below(mask)] = v;
+          Fn[base + lanes_below(mask)] = v * k;
           FBn[base + lanes_below(mask)] = pack_cand(L.dist[v], v);
         }
       }
     }
     __syncthreads();
     const int nnext = S.nfront[cur ^ 1];
-    if (tid == 0) {
-      S.stats[ST_BF_ROUNDS] += 1;
-      S.stats[ST_RELAX] += (int64_t)nf * k;
-      S.nfront[cur] = 0;
-    }
-    if (nnext == 0) return true;
+    rounds += 1;
+    relax += (int64_t)nf * k;
+    if (tid == 0) S.nfront[cur] = 0;
+    if (nnext == 0) { conv = true; break; }
     cur ^= 1;
   }
-  if (tid == 0) S.status = -5;   // LBDD_E_INTERNAL: negative cycle reachable
+  if (tid == 0) {
+    S.stats[ST_BF_ROUNDS] += rounds;
+    S.stats[ST_RELAX] += relax;
+    S.depth += ((int32_t)rounds * 16 - S.depth) / 8;
+    if (!conv) S.status = -5;   // LBDD_E_INTERNAL: negative cycle reachable
+  }
   __syncthreads();
-  return false;
+  return conv;
 }
 
-// Path search result from the labels a cycle search left on the same W
-// (it applied nothing, so the transfer graph is unchanged).  Both searches
-// relax the same transfer edges and s_in has no out-edges, so every center's
-// label and predecessor are the same; only s_in differs.  In synchronous
-// rounds s_in first reaches its final label best = min_u dist[u] + pe(u) in
-// the round after the earliest of those minimisers got its final label
+// Label of s_in from the center labels (dist, hop) of a search from s.
+// s_in has no out-edges, so the center labels do not depend on its in-edges
+// (cycle mode: W[u][s]; path mode: the penalty difference).  In synchronous
+// rounds s_in first reaches its final label best = min_u dist[u] + w(u, s_in)
+// in the round after the earliest of those minimisers got its final label
 // (hop[u]), and its predecessor is the smallest minimiser with that hop.
-__device__ __forceinline__ void path_from_labels(const InstView &I, const Lds &L, Scalars &S, int s) {
+// This also answers a path search from the labels of a cycle search that
+// applied nothing: both searches relax the same transfer edges.
+__device__ __forceinline__ void sin_from_labels(const InstView &I, const Lds &L, int s, int mode) {
   const int k = I.k;
   const int tid = threadIdx.x;
+  auto in_weight = [&](int u, int64_t &w) -> bool {
+    if (u == s || L.dist[u] == DIST_NONE) return false;
+    if (mode == 0) {
+      const uint64_t key = L.W[(int64_t)u * k + s];
+      if (key == KEY_NONE) return false;
+      w = key_delta(key);
+    } else {
+      w = (int64_t)(L.load[u] >= L.cap[u] ? L.pen[u] : 0) - L.pen[s];
+    }
+    return true;
+  };
   if (tid == 0) { L.red[0] = KEY_NONE; L.red[1] = KEY_NONE; }
   __syncthreads();
   for (int u = tid; u < k; u += NT) {
-    if (u == s || L.dist[u] == DIST_NONE) continue;
-    const int64_t c = L.dist[u] + (L.load[u] >= L.cap[u] ? L.pen[u] : 0) - L.pen[s];
-    atomicMin((unsigned long long *)&L.red[0], (unsigned long long)(c + DIST_BIAS));
+    int64_t w;
+    if (in_weight(u, w)) atomicMin((unsigned long long *)&L.red[0], (unsigned long long)(L.dist[u] + w + DIST_BIAS));
   }
   __syncthreads();
   const uint64_t best = L.red[0];
   for (int u = tid; u < k; u += NT) {
-    if (u == s || L.dist[u] == DIST_NONE || best == KEY_NONE) continue;
-    const int64_t c = L.dist[u] + (L.load[u] >= L.cap[u] ? L.pen[u] : 0) - L.pen[s];
-    if ((uint64_t)(c + DIST_BIAS) == best)
+    int64_t w;
+    if (best != KEY_NONE && in_weight(u, w) && (uint64_t)(L.dist[u] + w + DIST_BIAS) == best)
       atomicMin((unsigned long long *)&L.red[1], (unsigned long long)((uint64_t)L.hop[u] << 32 | (uint32_t)u));
   }
   __syncthreads();
@@ -487,7 +505,135 @@ __device__ __forceinline__ void path_from_labels(const InstView &I, const Lds &L
       L.dist[k] = (int64_t)best - DIST_BIAS;
       L.pred[k] = (int32_t)(uint32_t)L.red[1];
     }
-    S.stats[ST_PATH_DERIVED] += 1;
+  }
+  __syncthreads();
+}
+
+// Minimum over the 64 lanes of a wavefront (all lanes active), in every
+// lane: within rows of 16 lanes by DPP (swap neighbours, swap pairs, mirror
+// the half-row, mirror the row), then across rows by swapping odd with even
+// rows and the upper with the lower half.  A swap hands each lane either its
+// own value or its partner's in one of its two results, so taking the minimum
+// of both is right whichever it is.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_min_step(uint32_t x) {
+  const uint32_t y = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, true);
+  return y < x ? y : x;
+}
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+  x = dpp_min_step<0xb1>(x);     // quad_perm [1,0,3,2]
+  x = dpp_min_step<0x4e>(x);     // quad_perm [2,3,0,1]
+  x = dpp_min_step<0x141>(x);    // row_half_mirror
+  x = dpp_min_step<0x140>(x);    // row_mirror
+  const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+  x = min(x, min((uint32_t)p[0], (uint32_t)p[1]));
+  const auto q = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  x = min(x, min((uint32_t)q[0], (uint32_t)q[1]));
+  return x;
+}
+// 64-bit minimum as two 32-bit ones: high words, then low words of the lanes
+// holding the smallest high word.  The result is the same in every lane.
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_min_u32((uint32_t)(x >> 32)));
+  const uint32_t lo = wave_min_u32((uint32_t)(x >> 32) == hi ? (uint32_t)x : 0xffffffffu);
+  return (uint64_t)hi << 32 | (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
+}
+
+// Search from s in Dijkstra order by one wavefront, for when the node
+// potentials pot are feasible on every edge except those leaving s (the
+// search never enters s, so only its first hops can have negative reduced
+// weight w(u, v) + pot[u] - pot[v]).  Centers are settled in the order of
+// (reduced label, edges), which is a valid Dijkstra order for these pairs of
+// weights, so each center ends with its shortest distance and the fewest
+// edges among its shortest paths: the label and the round in which the
+// synchronous Bellman-Ford rounds fix it.  The predecessor is the smallest
+// settled center that reaches v with that pair (the smallest candidate of
+// that round).  Center v belongs to lane v % 64, slot v / 64; s_in follows
+// from the center labels.
+constexpr int64_t DJ_BIAS = 1ll << 45;   // reduced labels stay within +-2^44
+constexpr int DJ_MAX_NPL = 3;            // centers per lane (k <= 192)
+template <int NPL>
+__device__ __forceinline__ void dijkstra_wave(const InstView &I, const Lds &L, Scalars &S, int s) {
+  const int k = I.k;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const uint32_t *Whi = reinterpret_cast<const uint32_t *>(L.W) + 1;
+    // open: tentative key ((reduced label + DJ_BIAS) << 12 | edges) of an
+    // unsettled center, all ones once settled or while unreached; fin: the
+    // key a center was settled with
+    uint64_t open[NPL], fin[NPL];
+    int32_t pred[NPL];
+    int64_t pv[NPL];
+    bool done[NPL];
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+      const int v = lane + 64 * i;
+      pv[i] = v < k ? L.pot[v] : 0;
+      done[i] = v >= k;
+      pred[i] = -1;
+      open[i] = v == s ? (uint64_t)DJ_BIAS << 12 : KEY_NONE;
+      fin[i] = KEY_NONE;
+    }
+    for (int step = 0; step < k; ++step) {
+      uint64_t m = open[0];
+#pragma unroll
+      for (int i = 1; i < NPL; ++i) m = umin(m, open[i]);
+      m = wave_min_u64(m);
+      if (m == KEY_NONE) break;                  // the rest is unreachable
+      // the owner: first slot holding m, first lane of that slot
+      int oi = -1;
+      uint64_t om = 0;
+#pragma unroll
+      for (int i = NPL - 1; i >= 0; --i) {
+        const uint64_t b = __ballot(open[i] == m);
+        if (b) { oi = i; om = b; }
+      }
+      if (oi < 0) {                              // cannot happen: m is some lane's
+        if (lane == 0) S.status = -5;            // LBDD_E_INTERNAL
+        break;
+      }
+      const int ol = __builtin_ctzll(om);
+      const int u = ol + 64 * oi;
+      // the row of u and pot[u] in one round trip
+      uint32_t hw[NPL];
+      const uint32_t *row = Whi + 2 * (size_t)u * k;
+#pragma unroll
+      for (int i = 0; i < NPL; ++i) hw[i] = row[2 * (lane + 64 * i)];
+      const int64_t pot_u = L.pot[u];
+      const bool me = lane == ol;
+#pragma unroll
+      for (int i = 0; i < NPL; ++i) {
+        const bool hit = me && i == oi;
+        open[i] = hit ? KEY_NONE : open[i];
+        fin[i] = hit ? m : fin[i];
+        done[i] = done[i] || hit;
+      }
+      const uint64_t base = m + 1;               // one more edge
+#pragma unroll
+      for (int i = 0; i < NPL; ++i) {            // branch-free: selects only
+        const bool valid = !done[i] && hw[i] != 0xffffffffu;
+        const int64_t w = (int64_t)(int32_t)(hw[i] ^ 0x80000000u) + (pot_u - pv[i]);
+        const uint64_t c = valid ? base + ((uint64_t)w << 12) : KEY_NONE;
+        const bool lt = c < open[i];
+        const bool tie = valid && c == open[i] && u < pred[i];
+        open[i] = lt ? c : open[i];
+        pred[i] = (lt || tie) ? u : pred[i];
+      }
+    }
+    const int64_t pot_s = L.pot[s];
+    uint32_t deepest = 0;
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+      const int v = lane + 64 * i;
+      if (v >= k) continue;
+      const bool r = fin[i] != KEY_NONE;
+      L.dist[v] = r ? (int64_t)(fin[i] >> 12) - DJ_BIAS - pot_s + pv[i] : DIST_NONE;
+      L.pred[v] = r ? pred[i] : -1;
+      L.hop[v] = r ? (int32_t)(fin[i] & 4095) : -1;
+      deepest = r ? max(deepest, (uint32_t)(fin[i] & 4095)) : deepest;
+    }
+    deepest = ~wave_min_u32(~deepest);   // wave maximum
+    if (lane == 0) S.maxhop = (int32_t)deepest;
   }
   __syncthreads();
 }
@@ -497,14 +643,35 @@ __device__ __forceinline__ void path_from_labels(const InstView &I, const Lds &L
 // of the cycle search just run on the same W.  Returns true when nothing was
 // applied and the search succeeded: the labels in LDS then describe the
 // current W.
+// Without labels the search runs in Dijkstra order when the node potentials
+// allow it (cycle mode: feasible except on edges leaving s, which is all an
+// insert into s can break; path mode: feasible), else as Bellman-Ford rounds.
 template <bool WLDS>
 __device__ __forceinline__ bool refine(const InstView &I, const Lds &L, Scalars &S, int s, int mode,
                                        bool have_labels) {
   const int k = I.k;
   const int tid = threadIdx.x;
-  if (tid == 0) S.stats[mode == 0 ? ST_CYC_SEARCH : ST_PATH_SEARCH] += 1;
-  if (have_labels) path_from_labels(I, L, S, s);
-  else if (!bellman_ford(I, L, S, s, mode)) return false;
+  // cost model: a Bellman-Ford round costs about four Dijkstra steps, and a
+  // search takes (deepest hop + 1) rounds or k steps
+  const bool dijkstra = !have_labels && WLDS && S.pot_ok && k <= 64 * DJ_MAX_NPL && S.depth > 4 * k;   // depth is x16: rounds > k / 4
+  if (tid == 0) {
+    S.stats[mode == 0 ? ST_CYC_SEARCH : ST_PATH_SEARCH] += 1;
+    if (have_labels) S.stats[ST_PATH_DERIVED] += 1;
+    if (dijkstra) S.stats[ST_DIJKSTRA] += 1;
+  }
+  if (have_labels) {
+    sin_from_labels(I, L, s, 1);
+  } else if (dijkstra) {
+    if (k <= 64) dijkstra_wave<1>(I, L, S, s);
+    else if (k <= 128) dijkstra_wave<2>(I, L, S, s);
+    else dijkstra_wave<DJ_MAX_NPL>(I, L, S, s);
+    if (S.status != 0) return false;
+    if (tid == 0) S.depth += ((S.maxhop + 1) * 16 - S.depth) / 8;
+    sin_from_labels(I, L, s, mode);
+  } else {
+    if (!bellman_ford(I, L, S, s)) return false;
+    sin_from_labels(I, L, s, mode);
+  }
   const int64_t D = L.dist[k];
   if (D == DIST_NONE || D >= 0) {             // only strictly negative refinements apply
     if (!have_labels) adopt_potential(I, L, S, s);
@@ -564,15 +731,14 @@ __device__ __forceinline__ bool refine(const InstView &I, const Lds &L, Scalars 
   for (int e = 0; e < nmov; ++e) refill_center(I, L, S, L.mfrom[e]);
   if (tid == 0) S.stats[ST_T_RESCAN] += now() - t0;
   __syncthreads();
+  if (S.status == 0) retry_potential(I, L, S, s, nmov);
   return false;
 }
 
-// Iterations [r_begin, r_end) of one instance by the calling workgroup.
+// Layout of the dynamic LDS of one solving workgroup (solve_lds_bytes).
 template <bool WLDS>
-__device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, int64_t r_end,
-                                            unsigned char *lds, Scalars &S) {
+__device__ __forceinline__ Lds carve_lds(const InstView &I, unsigned char *lds) {
   const int k = I.k, K1 = k + 1;
-  const int tid = threadIdx.x;
   Lds L;
   unsigned char *p = lds;
   if (WLDS) { L.W = reinterpret_cast<uint64_t *>(p); p += (size_t)k * k * 8; }
@@ -596,6 +762,16 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
   L.trow = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
   p = lds + (((p - lds) + 7) & ~(ptrdiff_t)7);   // offsets keep the LDS address space
   L.wmin = reinterpret_cast<uint64_t *>(p);
+  return L;
+}
+
+// Iterations [r_begin, r_end) of one instance by the calling workgroup.
+template <bool WLDS>
+__device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, int64_t r_end,
+                                            unsigned char *lds, Scalars &S) {
+  const int k = I.k;
+  const int tid = threadIdx.x;
+  const Lds L = carve_lds<WLDS>(I, lds);
 
   if (WLDS)
     for (int64_t i = tid; i < (int64_t)k * k; i += NT) L.W[i] = I.W[i];
@@ -605,6 +781,7 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
     // the potential is not kept between launches: the first search rebuilds it
     // (an empty table is certified by the zero potential)
     S.pot_ok = r_begin == 0;
+    S.depth = 0;
     S.obj = I.scalars[SC_OBJECTIVE];
     S.status = (int32_t)I.scalars[SC_STATUS];
     for (int j = 0; j < SC_NSTATS; ++j) S.stats[j] = I.scalars[SC_STAT0 + j];

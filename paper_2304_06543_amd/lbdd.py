@@ -25,7 +25,8 @@ MAX_K = 2048
 STATS = ("cycles", "paths", "moves", "cycle_searches", "path_searches", "bf_rounds",
          "rows_scanned", "iterations", "cycle_searches_skipped",
          "ticks_allot", "ticks_cycle", "ticks_path", "ticks_rescan", "refills",
-         "tick_first", "tick_last", "relaxations", "paths_derived", "timer_khz")
+         "tick_first", "tick_last", "relaxations", "paths_derived", "dijkstra",
+         "potentials_kept", "timer_khz")
 
 # every symbol include/lbdd.h declares
 EXPORTS = ("lbdd_create", "lbdd_solve", "lbdd_solve_iters", "lbdd_solve_batch", "lbdd_objective",
