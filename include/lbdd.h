@@ -118,9 +118,9 @@ int lbdd_snapshot(lbdd_instance *h, int32_t *load, uint64_t *W, int64_t *order);
 /* Counters (int64, up to `count` of them, host memory):
  *   [0] cycles applied  [1] paths applied  [2] units moved
  *   [3] cycle searches run  [4] path searches run  [5] Bellman-Ford rounds
- *   [6] rows rescanned  [7] iterations done  [8] cycle searches skipped
- *       because the allotment left the anchor's transfer costs unchanged
- *   [6] counts member rows read by list refills (one column each)
+ *   [6] member rows read by list refills (one column each)
+ *   [7] iterations done  [8] cycle searches skipped because the node
+ *       potentials prove the table has no negative cycle
  *   [9] .. [12] device timer ticks spent in: allotment, cycle refinement,
  *       path refinement, list updates and refills after applied refinements
  *       (part of [10], [11])
@@ -137,6 +137,21 @@ int lbdd_snapshot(lbdd_instance *h, int32_t *load, uint64_t *W, int64_t *order);
  *   [20] device timer frequency in kHz
  * Synchronises.  Returns the number of counters written (>= 0). */
 int lbdd_stats(lbdd_instance *h, int64_t *out, int32_t count);
+
+/* Per-instance options (none changes a result, only how fast it comes).
+ *   LBDD_OPT_SEARCH_RATIO  int64 in [0, 2^20]: the cost of one Bellman-Ford
+ *     round in Dijkstra steps, x16.  A refinement search runs in Dijkstra
+ *     order (when the node potentials allow it and k <= 192 with the table in
+ *     LDS) if the running mean of the rounds a search needs, times the ratio,
+ *     exceeds k.  0: always Bellman-Ford; 2^20: Dijkstra whenever allowed.
+ *     New instances start with the value lbdd_tune_search recorded for their
+ *     k in this process, else 64.
+ * lbdd_set_option takes effect at the next solve launch.  Both synchronise
+ * the instance's stream.  Errors: LBDD_E_INVAL (NULL, unknown option, value
+ * out of range), LBDD_E_DEVICE. */
+#define LBDD_OPT_SEARCH_RATIO 1
+int lbdd_set_option(lbdd_instance *h, int32_t option, int64_t value);
+int lbdd_get_option(lbdd_instance *h, int32_t option, int64_t *value);
 
 /* Solve many instances in one persistent launch (growth of Algorithm 2 to a
  * batch of independent instances; each instance's result is the one
@@ -229,6 +244,42 @@ size_t lbdd_best_transfers_work_bytes(int32_t k, int64_t n);
 int lbdd_best_transfers(int32_t k, int64_t n, const int32_t *cm, const int32_t *assign,
                         const int32_t *rank, uint64_t *W, void *work, uint32_t flags,
                         void *hip_stream);
+
+/* ---- autotuner -------------------------------------------------------------
+ * Both calls time choices that leave every result unchanged and record the
+ * fastest in a lock-guarded table of this process.  An instance takes its
+ * search ratio from the table when it is created; a scan looks its tile
+ * configuration up when it is launched.
+ *
+ * lbdd_tune_search: creates a fresh instance from the inputs (arguments as
+ * lbdd_create) once per candidate search ratio (0, 32, 64, 128, 2^20), times
+ * its first `iters` iterations with HIP events on `hip_stream`, checks that
+ * all candidates reach the same objective, and records the fastest ratio for
+ * this k (used by later lbdd_create calls).  Writes it to *ratio_out and the
+ * candidates' times in ms to ms_out[0 .. count-1].  Synchronises.  Returns
+ * the number of candidates (5), or LBDD_E_INVAL, LBDD_E_NOMEM, LBDD_E_DEVICE,
+ * LBDD_E_INTERNAL (candidates disagreed). */
+int lbdd_tune_search(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity,
+                     const int32_t *penalty, uint32_t flags, int64_t iters, void *hip_stream,
+                     int64_t *ratio_out, float *ms_out, int32_t count);
+
+/* lbdd_tune_best_transfers: arguments as lbdd_best_transfers (n >= 1).
+ * Groups the units once, then times the streaming pass of every tile
+ * configuration that covers k columns (lanes per row, column groups per
+ * lane, one or two resident waves of workgroups) `reps` times after a
+ * warm-up, checks on the device that each produced the default's table, and
+ * records the fastest for this k and load width (16-byte loads need
+ * k % 4 == 0 and a 16-byte aligned cm).  On return W holds the table of the
+ * inputs and work their grouping, as after lbdd_best_transfers.
+ *   config_out  [4] int32: columns per load, lanes per row, column groups per
+ *               lane, waves of workgroups of the chosen configuration
+ *   ms_out      [2] float: mean ms of the default and of the chosen one
+ * Synchronises.  Returns the number of configurations timed, or
+ * LBDD_E_INVAL, LBDD_E_NOMEM, LBDD_E_DEVICE, LBDD_E_INTERNAL (a configuration
+ * produced another table). */
+int lbdd_tune_best_transfers(int32_t k, int64_t n, const int32_t *cm, const int32_t *assign,
+                             const int32_t *rank, uint64_t *W, void *work, int32_t reps,
+                             void *hip_stream, int32_t *config_out, float *ms_out);
 
 #ifdef __cplusplus
 }

@@ -139,6 +139,7 @@ int lbdd_create(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity
   const int32_t *cm_dev = cm;
   int32_t *cm_tmp = nullptr, *bad = nullptr;
   void *work = nullptr;
+  int64_t ratio = 0;                 // read by an async copy: lives until the sync below
   int rc = LBDD_OK;
   do {
     if (!(flags & LBDD_CM_DEVICE)) {
@@ -160,6 +161,10 @@ int lbdd_create(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity
       rc = hip_fail(e, "setup kernels"); break;
     }
     if ((e = lbdd::launch_init_state(h->view(), h->st)) != hipSuccess) { rc = hip_fail(e, "init kernel"); break; }
+    ratio = lbdd::tuned_search_ratio(k);
+    if ((e = hipMemcpyAsync(h->scalars + lbdd::SC_RATIO, &ratio, sizeof ratio, hipMemcpyHostToDevice, h->st)) != hipSuccess) {
+      rc = hip_fail(e, "init search ratio"); break;
+    }
     int32_t bad_h = 0;
     if ((e = hipMemcpyAsync(&bad_h, bad, 4, hipMemcpyDeviceToHost, h->st)) != hipSuccess ||
         (e = hipStreamSynchronize(h->st)) != hipSuccess) {
@@ -173,6 +178,24 @@ int lbdd_create(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity
   if (bad) (void)hipFreeAsync(bad, h->st);
   if (rc != LBDD_OK) { release(h); return rc; }
   *out = h;
+  return LBDD_OK;
+}
+
+int lbdd_set_option(lbdd_instance *h, int32_t option, int64_t value) {
+  if (!h) return fail(LBDD_E_INVAL, "NULL handle");
+  if (option != LBDD_OPT_SEARCH_RATIO) return fail(LBDD_E_INVAL, "unknown option %d", option);
+  if (value < 0 || value > lbdd::MAX_SEARCH_RATIO)
+    return fail(LBDD_E_INVAL, "search ratio %lld outside [0, 2^20]", (long long)value);
+  HIP_TRY(copy_sync(h->scalars + lbdd::SC_RATIO, &value, sizeof value, hipMemcpyHostToDevice, h->st),
+          "set option");
+  return LBDD_OK;
+}
+
+int lbdd_get_option(lbdd_instance *h, int32_t option, int64_t *value) {
+  if (!h || !value) return fail(LBDD_E_INVAL, "NULL argument");
+  if (option != LBDD_OPT_SEARCH_RATIO) return fail(LBDD_E_INVAL, "unknown option %d", option);
+  HIP_TRY(copy_sync(value, h->scalars + lbdd::SC_RATIO, sizeof *value, hipMemcpyDeviceToHost, h->st),
+          "get option");
   return LBDD_OK;
 }
 

@@ -69,8 +69,12 @@ enum : int {
   SC_STATUS = 2,        // 0 ok, else an LBDD_E_* code
   SC_STAT0 = 3,         // first of the counters reported by lbdd_stats
   SC_NSTATS = 20,
-  SC_COUNT = SC_STAT0 + SC_NSTATS
+  SC_RATIO = SC_STAT0 + SC_NSTATS,   // search-choice ratio (x16, see refine in solve.hip)
+  SC_COUNT = SC_RATIO + 1
 };
+// A Bellman-Ford round costs about this many (x16) Dijkstra steps unless tuned.
+constexpr int64_t DEFAULT_SEARCH_RATIO = 64;
+constexpr int64_t MAX_SEARCH_RATIO = 1 << 20;   // Dijkstra whenever it applies
 enum : int {
   ST_CYCLES = 0, ST_PATHS, ST_MOVES, ST_CYC_SEARCH, ST_PATH_SEARCH, ST_BF_ROUNDS,
   ST_ROWS_SCANNED, ST_ITERS, ST_CYC_SKIPPED,
@@ -126,7 +130,25 @@ hipError_t launch_solve_batch(const BatchItem *items_dev, int32_t m, int32_t *he
 int device_cus();
 hipError_t launch_service(ServiceCtl *ctl, const ServiceJob *ring, int32_t ring_size, int64_t *done,
                           int64_t *head, int64_t idle_ticks, int workers, hipStream_t st);
-// scan.hip: whole-matrix best-transfer table
+// tune.hip: values chosen by the autotuner for this process
+int64_t tuned_search_ratio(int32_t k);
+// scan.hip: whole-matrix best-transfer table.  A tile configuration: VEC
+// columns per load, LPR lanes per row, NP column groups per lane, MULT
+// resident waves of workgroups.
+struct ScanCfg {
+  int32_t vec, lpr, np, mult;
+};
+bool scan_cfg_valid(int32_t k, const ScanCfg &c);
+ScanCfg scan_default_cfg(int32_t k, bool vec4);
+int scan_candidates(int32_t k, bool vec4, ScanCfg *out, int max);
+void scan_set_tuned(int32_t k, bool vec4, const ScanCfg &c);
+hipError_t launch_scan_group(int32_t k, int64_t n, const int32_t *assign, const int32_t *rank,
+                             uint64_t *W, void *work, bool regroup, hipStream_t st);
+hipError_t launch_scan_only(int32_t k, const int32_t *cm, void *work, const ScanCfg &c,
+                            uint64_t *W, hipStream_t st);
+bool scan_vec4_ok(int32_t k, const int32_t *cm);
+hipError_t launch_differ(const uint64_t *a, const uint64_t *b, int64_t count, int32_t *flag,
+                         hipStream_t st);
 size_t scan_work_bytes(int32_t k, int64_t n);
 hipError_t launch_full_scan(int32_t k, int64_t n, const int32_t *cm, const int32_t *assign,
                             const int32_t *rank, uint64_t *W, void *work, bool reuse_grouping,

@@ -15,6 +15,9 @@
 // workgroup with LDS atomics and leave with one global atomic min per column
 // per segment.  Keys are unique, so the result does not depend on the order
 // in which rows or segments are reduced.
+#include <map>
+#include <mutex>
+
 #include "lbdd_dev.hpp"
 
 namespace lbdd {
@@ -248,72 +251,174 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_kernel(int32_t k, const int
   }
 }
 
-// One resident wave of workgroups: as many per CU as registers and LDS allow.
+// MULT resident waves of workgroups: as many per CU as registers and LDS allow.
 template <int VEC, int LPR, int NP>
-hipError_t launch_scan_t(int32_t k, const int32_t *cm, const ScanWork &w, int cus,
+hipError_t launch_scan_t(int32_t k, const int32_t *cm, const ScanWork &w, int cus, int mult,
                          uint64_t *W, hipStream_t st) {
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
       &per_cu, reinterpret_cast<const void *>(&scan_kernel<VEC, LPR, NP>), SCAN_THREADS, (size_t)k * 8);
   if (e != hipSuccess) return e;
-  const int blocks = cus * (per_cu > 0 ? per_cu : 1);
+  const int blocks = cus * (per_cu > 0 ? per_cu : 1) * mult;
   scan_kernel<VEC, LPR, NP><<<blocks, SCAN_THREADS, (size_t)k * 8, st>>>(k, cm, w.units, w.offset, W);
   return hipGetLastError();
 }
 
-template <int VEC>
-hipError_t dispatch_scan(int32_t k, const int32_t *cm, const ScanWork &w, int cus,
-                         uint64_t *W, hipStream_t st) {
-  const int groups = (k + VEC - 1) / VEC;      // column groups per row
-  if (groups <= 1) return launch_scan_t<VEC, 1, 1>(k, cm, w, cus, W, st);
-  if (groups <= 2) return launch_scan_t<VEC, 2, 1>(k, cm, w, cus, W, st);
-  if (groups <= 4) return launch_scan_t<VEC, 4, 1>(k, cm, w, cus, W, st);
-  if (groups <= 8) return launch_scan_t<VEC, 8, 1>(k, cm, w, cus, W, st);
-  if (groups <= 16) return launch_scan_t<VEC, 16, 1>(k, cm, w, cus, W, st);
-  if (groups <= 32) return launch_scan_t<VEC, 32, 1>(k, cm, w, cus, W, st);
-  if (groups <= 64) return launch_scan_t<VEC, 64, 1>(k, cm, w, cus, W, st);
-  if (groups <= 128) return launch_scan_t<VEC, 64, 2>(k, cm, w, cus, W, st);
-  if (groups <= 256) return launch_scan_t<VEC, 64, 4>(k, cm, w, cus, W, st);
-  if (groups <= 512 || VEC == 4) return launch_scan_t<VEC, 64, 8>(k, cm, w, cus, W, st);
-  if constexpr (VEC == 1) {   // k <= LBDD_MAX_K = 2048
-    if (groups <= 1024) return launch_scan_t<VEC, 64, 16>(k, cm, w, cus, W, st);
-    return launch_scan_t<VEC, 64, 32>(k, cm, w, cus, W, st);
-  }
+// The instantiated tile shapes (VEC, LPR, NP).
+struct Shape {
+  int vec, lpr, np;
+};
+constexpr Shape SHAPES[] = {
+    {4, 1, 1},  {4, 2, 1},  {4, 4, 1},  {4, 8, 1},  {4, 16, 1}, {4, 16, 2}, {4, 16, 4},
+    {4, 16, 8}, {4, 32, 1}, {4, 32, 2}, {4, 32, 4}, {4, 32, 8}, {4, 64, 1}, {4, 64, 2},
+    {4, 64, 4}, {4, 64, 8}, {1, 1, 1},  {1, 2, 1},  {1, 4, 1},  {1, 8, 1},  {1, 16, 1},
+    {1, 32, 1}, {1, 64, 1}, {1, 64, 2}, {1, 64, 4}, {1, 64, 8}, {1, 64, 16}, {1, 64, 32},
+};
+
+hipError_t launch_shape(const ScanCfg &c, int32_t k, const int32_t *cm, const ScanWork &w, int cus,
+                        uint64_t *W, hipStream_t st) {
+#define LBDD_SCAN_CASE(V, L, P) \
+  if (c.vec == V && c.lpr == L && c.np == P) return launch_scan_t<V, L, P>(k, cm, w, cus, c.mult, W, st);
+  LBDD_SCAN_CASE(4, 1, 1) LBDD_SCAN_CASE(4, 2, 1) LBDD_SCAN_CASE(4, 4, 1) LBDD_SCAN_CASE(4, 8, 1)
+  LBDD_SCAN_CASE(4, 16, 1) LBDD_SCAN_CASE(4, 16, 2) LBDD_SCAN_CASE(4, 16, 4) LBDD_SCAN_CASE(4, 16, 8)
+  LBDD_SCAN_CASE(4, 32, 1) LBDD_SCAN_CASE(4, 32, 2) LBDD_SCAN_CASE(4, 32, 4) LBDD_SCAN_CASE(4, 32, 8)
+  LBDD_SCAN_CASE(4, 64, 1) LBDD_SCAN_CASE(4, 64, 2) LBDD_SCAN_CASE(4, 64, 4) LBDD_SCAN_CASE(4, 64, 8)
+  LBDD_SCAN_CASE(1, 1, 1) LBDD_SCAN_CASE(1, 2, 1) LBDD_SCAN_CASE(1, 4, 1) LBDD_SCAN_CASE(1, 8, 1)
+  LBDD_SCAN_CASE(1, 16, 1) LBDD_SCAN_CASE(1, 32, 1) LBDD_SCAN_CASE(1, 64, 1) LBDD_SCAN_CASE(1, 64, 2)
+  LBDD_SCAN_CASE(1, 64, 4) LBDD_SCAN_CASE(1, 64, 8) LBDD_SCAN_CASE(1, 64, 16) LBDD_SCAN_CASE(1, 64, 32)
+#undef LBDD_SCAN_CASE
   return hipErrorInvalidValue;
 }
 
+// configurations chosen by the autotuner, per (k, load width)
+std::mutex g_tuned_mu;
+std::map<int64_t, ScanCfg> g_tuned;
+int64_t tuned_key(int32_t k, bool vec4) { return (int64_t)k * 2 + (vec4 ? 1 : 0); }
+
 }  // namespace
+
+bool scan_cfg_valid(int32_t k, const ScanCfg &c) {
+  if (c.mult < 1 || c.mult > 4) return false;
+  if ((int64_t)c.lpr * c.np * c.vec < k) return false;   // every column has a lane
+  for (const Shape &sh : SHAPES)
+    if (sh.vec == c.vec && sh.lpr == c.lpr && sh.np == c.np) return true;
+  return false;
+}
+
+// Lanes per row follow the number of column groups up to a wavefront, then
+// each lane takes more groups.
+ScanCfg scan_default_cfg(int32_t k, bool vec4) {
+  const int vec = vec4 ? 4 : 1;
+  const int groups = (k + vec - 1) / vec;
+  ScanCfg c{vec, 64, 1, 1};
+  if (groups <= 64) {
+    int l = 1;
+    while (l < groups) l *= 2;
+    c.lpr = l;
+  } else {
+    int np = 2;
+    while (64 * np < groups) np *= 2;
+    c.np = np;
+  }
+  return c;
+}
+
+// Candidates: every instantiated shape that covers k columns without more
+// than four times the lanes it needs, with one or two resident waves of
+// workgroups; the default configuration comes first.
+int scan_candidates(int32_t k, bool vec4, ScanCfg *out, int max) {
+  int m = 0;
+  const ScanCfg d = scan_default_cfg(k, vec4);
+  if (m < max) out[m++] = d;
+  for (const Shape &sh : SHAPES) {
+    if (sh.vec != (vec4 ? 4 : 1)) continue;
+    const int64_t cols = (int64_t)sh.lpr * sh.np * sh.vec;
+    if (cols < k || cols > 4 * (int64_t)k + 4 * sh.vec) continue;
+    for (int mult = 1; mult <= 2; ++mult) {
+      const ScanCfg c{sh.vec, sh.lpr, sh.np, mult};
+      if (c.lpr == d.lpr && c.np == d.np && c.mult == d.mult) continue;
+      if (m < max) out[m++] = c;
+    }
+  }
+  return m;
+}
+
+void scan_set_tuned(int32_t k, bool vec4, const ScanCfg &c) {
+  std::lock_guard<std::mutex> g(g_tuned_mu);
+  g_tuned[tuned_key(k, vec4)] = c;
+}
+
+namespace {
+__global__ void differ_kernel(const uint64_t *__restrict__ a, const uint64_t *__restrict__ b,
+                              int64_t count, int32_t *flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    bad |= a[i] != b[i];
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+}  // namespace
+
+// *flag |= (a != b) over count entries (the flag is not cleared here).
+hipError_t launch_differ(const uint64_t *a, const uint64_t *b, int64_t count, int32_t *flag,
+                         hipStream_t st) {
+  differ_kernel<<<256, 256, 0, st>>>(a, b, count, flag);
+  return hipGetLastError();
+}
+
+bool scan_vec4_ok(int32_t k, const int32_t *cm) { return (k % 4 == 0) && ((uintptr_t)cm % 16 == 0); }
+
 
 size_t scan_work_bytes(int32_t k, int64_t n) {
   return 2 * align_up((size_t)k * 4) + align_up((size_t)(k + 1) * 8) + align_up((size_t)n * 8);
 }
 
-hipError_t launch_full_scan(int32_t k, int64_t n, const int32_t *cm, const int32_t *assign,
-                            const int32_t *rank, uint64_t *W, void *work, bool reuse_grouping,
-                            hipStream_t st) {
+// Clear W and, unless an earlier call's grouping is reused, group the units
+// by center.
+hipError_t launch_scan_group(int32_t k, int64_t n, const int32_t *assign, const int32_t *rank,
+                             uint64_t *W, void *work, bool regroup, hipStream_t st) {
   ScanWork w = carve(work, k);
   hipError_t e;
   // the counts are cleared too, unless the grouping of a previous call is reused
-  fill_kernel<<<256, 256, 0, st>>>((int64_t)k * k, KEY_NONE, W, reuse_grouping ? 0 : k, w.count, w.cursor);
+  fill_kernel<<<256, 256, 0, st>>>((int64_t)k * k, KEY_NONE, W, regroup ? k : 0, w.count, w.cursor);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (n == 0) return hipSuccess;
-  if (!reuse_grouping) {   // group the units by center
-    int64_t hb = (n + 1023) / 1024;
-    if (hb > 2048) hb = 2048;
-    histogram_kernel<<<(unsigned)hb, 1024, (size_t)k * 4, st>>>(k, n, assign, w.count);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    offsets_kernel<<<1, 1024, 0, st>>>(k, w.count, w.offset);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int64_t per_block = (int64_t)SCATTER_THREADS * SCATTER_ITEMS;
-    scatter_kernel<<<(unsigned)((n + per_block - 1) / per_block), SCATTER_THREADS, (size_t)k * 8, st>>>(
-        k, n, assign, rank, w.offset, w.cursor, w.units);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
+  if (n == 0 || !regroup) return hipSuccess;
+  int64_t hb = (n + 1023) / 1024;
+  if (hb > 2048) hb = 2048;
+  histogram_kernel<<<(unsigned)hb, 1024, (size_t)k * 4, st>>>(k, n, assign, w.count);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  offsets_kernel<<<1, 1024, 0, st>>>(k, w.count, w.offset);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int64_t per_block = (int64_t)SCATTER_THREADS * SCATTER_ITEMS;
+  scatter_kernel<<<(unsigned)((n + per_block - 1) / per_block), SCATTER_THREADS, (size_t)k * 8, st>>>(
+      k, n, assign, rank, w.offset, w.cursor, w.units);
+  return hipGetLastError();
+}
+
+// The streaming pass over the grouped units with tile configuration c.
+hipError_t launch_scan_only(int32_t k, const int32_t *cm, void *work, const ScanCfg &c, uint64_t *W,
+                            hipStream_t st) {
+  if (!scan_cfg_valid(k, c)) return hipErrorInvalidValue;
   int dev = 0, cus = 0;
+  hipError_t e;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-  const bool vec = (k % 4 == 0) && ((uintptr_t)cm % 16 == 0);
-  return vec ? dispatch_scan<4>(k, cm, w, cus, W, st) : dispatch_scan<1>(k, cm, w, cus, W, st);
+  return launch_shape(c, k, cm, carve(work, k), cus, W, st);
+}
+
+hipError_t launch_full_scan(int32_t k, int64_t n, const int32_t *cm, const int32_t *assign,
+                            const int32_t *rank, uint64_t *W, void *work, bool reuse_grouping,
+                            hipStream_t st) {
+  hipError_t e = launch_scan_group(k, n, assign, rank, W, work, !reuse_grouping, st);
+  if (e != hipSuccess || n == 0) return e;
+  const bool vec4 = scan_vec4_ok(k, cm);
+  ScanCfg c = scan_default_cfg(k, vec4);
+  {
+    std::lock_guard<std::mutex> g(g_tuned_mu);
+    auto it = g_tuned.find(tuned_key(k, vec4));
+    if (it != g_tuned.end()) c = it->second;
+  }
+  return launch_scan_only(k, cm, work, c, W, st);
 }
 
 }  // namespace lbdd

@@ -75,6 +75,7 @@ struct Scalars {
   int32_t nrefill;
   int32_t pot_ok;   // pot is feasible for the current W
   int32_t vacant;
+  int32_t ratio;    // cost of a Bellman-Ford round in Dijkstra steps, x16
   int32_t depth;    // running mean of (deepest hop + 1) of recent searches, x16
   int32_t maxhop;   // deepest hop of the last search in Dijkstra order
 };
@@ -651,9 +652,11 @@ __device__ __forceinline__ bool refine(const InstView &I, const Lds &L, Scalars 
                                        bool have_labels) {
   const int k = I.k;
   const int tid = threadIdx.x;
-  // cost model: a Bellman-Ford round costs about four Dijkstra steps, and a
-  // search takes (deepest hop + 1) rounds or k steps
-  const bool dijkstra = !have_labels && WLDS && S.pot_ok && k <= 64 * DJ_MAX_NPL && S.depth > 4 * k;   // depth is x16: rounds > k / 4
+  // cost model: a search takes (deepest hop + 1) Bellman-Ford rounds or k
+  // Dijkstra steps, and a round costs `ratio` steps (both x16; the default
+  // is 4 steps, the autotuner measures it)
+  const bool dijkstra = !have_labels && WLDS && S.pot_ok && k <= 64 * DJ_MAX_NPL &&
+                        (int64_t)S.depth * S.ratio > 256 * (int64_t)k;
   if (tid == 0) {
     S.stats[mode == 0 ? ST_CYC_SEARCH : ST_PATH_SEARCH] += 1;
     if (have_labels) S.stats[ST_PATH_DERIVED] += 1;
@@ -782,6 +785,7 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
     // (an empty table is certified by the zero potential)
     S.pot_ok = r_begin == 0;
     S.depth = 0;
+    S.ratio = (int32_t)min(max(I.scalars[SC_RATIO], (int64_t)0), MAX_SEARCH_RATIO);
     S.obj = I.scalars[SC_OBJECTIVE];
     S.status = (int32_t)I.scalars[SC_STATUS];
     for (int j = 0; j < SC_NSTATS; ++j) S.stats[j] = I.scalars[SC_STAT0 + j];

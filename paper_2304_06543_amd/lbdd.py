@@ -34,7 +34,8 @@ EXPORTS = ("lbdd_create", "lbdd_solve", "lbdd_solve_iters", "lbdd_solve_batch", 
            "lbdd_destroy", "lbdd_last_error", "lbdd_best_transfers_work_bytes",
            "lbdd_best_transfers", "lbdd_server_create", "lbdd_server_submit",
            "lbdd_server_poll", "lbdd_server_wait", "lbdd_server_result", "lbdd_server_stats",
-           "lbdd_server_destroy")
+           "lbdd_server_destroy", "lbdd_set_option", "lbdd_get_option", "lbdd_tune_search",
+           "lbdd_tune_best_transfers")
 JOB_QUEUED, JOB_RUNNING, JOB_DONE = 0, 1, 2
 SERVER_STATS = ("submitted", "admitted", "finished", "failed", "kernel_launches",
                 "peak_jobs", "peak_bytes", "bytes_now", "workers")
@@ -78,6 +79,10 @@ def load(path: str = LIB_PATH):
         "lbdd_server_result": ([P, C.c_uint64, P, P], C.c_int),
         "lbdd_server_stats": ([P, P, I32], C.c_int),
         "lbdd_server_destroy": ([P], None),
+        "lbdd_set_option": ([P, I32, I64], C.c_int),
+        "lbdd_get_option": ([P, I32, C.POINTER(I64)], C.c_int),
+        "lbdd_tune_search": ([I32, I64, P, P, P, U32, I64, P, C.POINTER(I64), P, I32], C.c_int),
+        "lbdd_tune_best_transfers": ([I32, I64, P, P, P, P, P, I32, P, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -106,6 +111,31 @@ def _host_i32(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a), dtype=np.int32)
 
 
+OPT_SEARCH_RATIO = 1
+
+
+def _create_args(cm, capacity, penalty):
+    """(k, n, cm pointer, flags, capacity, penalty, buffer to keep alive) for
+    lbdd_create from a torch cuda tensor or a host array."""
+    cap = _host_i32(capacity)
+    pen = _host_i32(penalty)
+    if hasattr(cm, "is_cuda") and cm.is_cuda:
+        import torch
+        if cm.dtype != torch.int32 or not cm.is_contiguous() or cm.dim() != 2:
+            raise ValueError("cm must be a contiguous 2-D int32 tensor")
+        n, k = cm.shape
+        ptr, flags, keep = C.c_void_p(cm.data_ptr()), CM_DEVICE, cm
+    else:
+        cmh = _host_i32(cm)
+        if cmh.ndim != 2:
+            raise ValueError("cm must be 2-D [n][k]")
+        n, k = cmh.shape
+        ptr, flags, keep = cmh.ctypes.data_as(C.c_void_p), 0, cmh
+    if cap.shape != (k,) or pen.shape != (k,):
+        raise ValueError("capacity and penalty need k entries")
+    return int(k), int(n), ptr, flags, cap, pen, keep
+
+
 class Instance:
     """One LBDD instance living on the GPU (lbdd_create ... lbdd_destroy)."""
 
@@ -113,28 +143,22 @@ class Instance:
         lib = load()
         self._lib = lib
         self._h = C.c_void_p()
-        cap = _host_i32(capacity)
-        pen = _host_i32(penalty)
-        if hasattr(cm, "is_cuda") and cm.is_cuda:
-            import torch
-            if cm.dtype != torch.int32 or not cm.is_contiguous() or cm.dim() != 2:
-                raise ValueError("cm must be a contiguous 2-D int32 tensor")
-            n, k = cm.shape
-            ptr, flags, self._keep = C.c_void_p(cm.data_ptr()), CM_DEVICE, cm
-        else:
-            cmh = _host_i32(cm)
-            if cmh.ndim != 2:
-                raise ValueError("cm must be 2-D [n][k]")
-            n, k = cmh.shape
-            ptr, flags, self._keep = cmh.ctypes.data_as(C.c_void_p), 0, cmh
-        if cap.shape != (k,) or pen.shape != (k,):
-            raise ValueError("capacity and penalty need k entries")
-        self.k, self.n = int(k), int(n)
+        k, n, ptr, flags, cap, pen, keep = _create_args(cm, capacity, penalty)
+        self.k, self.n = k, n
         self._stream = _stream_ptr(stream)
-        _check(lib.lbdd_create(self.k, self.n, ptr, cap.ctypes.data_as(C.c_void_p),
+        _check(lib.lbdd_create(k, n, ptr, cap.ctypes.data_as(C.c_void_p),
                                pen.ctypes.data_as(C.c_void_p), flags, self._stream,
                                C.byref(self._h)))
-        self._keep = None
+        del keep
+
+    def set_option(self, option: int, value: int):
+        _check(self._lib.lbdd_set_option(self._h, int(option), int(value)))
+        return self
+
+    def get_option(self, option: int) -> int:
+        out = C.c_int64()
+        _check(self._lib.lbdd_get_option(self._h, int(option), C.byref(out)))
+        return out.value
 
     def solve(self):
         _check(self._lib.lbdd_solve(self._h))
@@ -243,6 +267,43 @@ def best_transfers(cm, assign, rank, W=None, work=None, stream=None, reuse_group
                                       SCAN_REUSE_GROUPING if reuse_grouping else 0,
                                       _stream_ptr(stream)))
     return W
+
+
+def tune_search(cm, capacity, penalty, iters: int, stream=None):
+    """Autotune the search choice for this k on a prefix of `iters`
+    iterations (lbdd_tune_search).  Returns (ratio, [ms per candidate])."""
+    k, n, ptr, flags, cap, pen, keep = _create_args(cm, capacity, penalty)
+    ratio = C.c_int64()
+    ms = (C.c_float * 8)()
+    m = _check(load().lbdd_tune_search(k, n, ptr, cap.ctypes.data_as(C.c_void_p),
+                                       pen.ctypes.data_as(C.c_void_p), flags, int(iters),
+                                       _stream_ptr(stream), C.byref(ratio),
+                                       C.cast(ms, C.c_void_p), 8))
+    del keep
+    return ratio.value, [float(ms[i]) for i in range(m)]
+
+
+def tune_best_transfers(cm, assign, rank, reps: int = 5, W=None, work=None, stream=None):
+    """Autotune the whole-matrix scan's tiles for this k (lbdd_tune_best_transfers).
+    Returns (W, (vec, lanes_per_row, groups_per_lane, waves), (default_ms, tuned_ms), count)."""
+    import torch
+    n, k = cm.shape
+    for t in (cm, assign, rank):
+        if not (t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()):
+            raise ValueError("cm, assign and rank must be contiguous int32 cuda tensors")
+    if W is None:
+        W = torch.empty((k, k), dtype=torch.int64, device=cm.device)
+    if work is None:
+        work = torch.empty(best_transfers_work_bytes(k, n), dtype=torch.uint8, device=cm.device)
+    cfg = (C.c_int32 * 4)()
+    ms = (C.c_float * 2)()
+    m = _check(load().lbdd_tune_best_transfers(int(k), int(n), C.c_void_p(cm.data_ptr()),
+                                               C.c_void_p(assign.data_ptr()),
+                                               C.c_void_p(rank.data_ptr()), C.c_void_p(W.data_ptr()),
+                                               C.c_void_p(work.data_ptr()), int(reps),
+                                               _stream_ptr(stream), C.cast(cfg, C.c_void_p),
+                                               C.cast(ms, C.c_void_p)))
+    return W, tuple(int(x) for x in cfg), (float(ms[0]), float(ms[1])), m
 
 
 class Server:

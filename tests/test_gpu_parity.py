@@ -144,6 +144,26 @@ def test_config_c2_bit_exact_against_stored_oracle(lb):
     assert obj == pins.eq1(*inst.arrays(), a)
 
 
+def test_every_search_kind_runs_bit_exact(lb):
+    """The solver answers a refinement search in one of several exact ways:
+    Bellman-Ford rounds, Dijkstra order on feasible node potentials, the
+    labels of a cycle search that applied nothing, or no search at all when
+    the potentials certify there is no negative cycle.  These instances use
+    every one of them, and the results still equal the oracle's."""
+    seen = {}
+    for seed, k in ((41, 12), (42, 40), (43, 100)):
+        inst = L.random_small(k=k, n=4000, seed=seed, cm_hi=300, pen_hi=400)
+        say("search kinds", inst.name)
+        ref = oracle.solve(*inst.arrays())
+        obj, a, st = gpu_solve(lb, inst)
+        assert obj == ref.objective and np.array_equal(a, ref.assign)
+        for key in ("bf_rounds", "dijkstra", "paths_derived", "potentials_kept",
+                    "cycle_searches_skipped", "cycles", "paths"):
+            seen[key] = seen.get(key, 0) + st[key]
+    say("search kinds", seen)
+    assert all(v > 0 for v in seen.values()), seen
+
+
 def test_solve_is_deterministic(lb):
     inst = L.random_small(k=24, n=5000, seed=3, cm_hi=40, pen_hi=200)
     r1 = gpu_solve(lb, inst)
@@ -257,3 +277,75 @@ def test_c3_prefix_bit_exact_and_invariants(lb):
         assert np.array_equal(np.bincount(a[a >= 0], minlength=inst.k), load)
         assert np.array_equal(W, oracle.best_transfers(inst.cm, a, rank))
         assert not pins.has_negative_cycle(W)
+
+
+# ---------------------------------------------------- options and autotuner
+@pytest.mark.parametrize("k", [12, 40, 100, 131])
+def test_search_ratio_extremes_bit_exact(lb, k):
+    """All Bellman-Ford rounds (ratio 0) and Dijkstra order whenever the
+    potentials allow it (ratio 2^20) reach the oracle's allotment."""
+    import torch
+    inst = L.random_small(k=k, n=3000, seed=900 + k, cm_hi=400, pen_hi=300)
+    say("search ratio", inst.name)
+    ref = oracle.solve(*inst.arrays())
+    for ratio in (0, 1 << 20):
+        with lb.Instance(torch.from_numpy(inst.cm).cuda(), inst.cap, inst.pen) as I:
+            I.set_option(lb.OPT_SEARCH_RATIO, ratio)
+            assert I.get_option(lb.OPT_SEARCH_RATIO) == ratio
+            I.solve()
+            obj, a, st = I.objective(), I.assignment(), I.stats()
+        say("  ratio", ratio, "dijkstra", st["dijkstra"], "bf_rounds", st["bf_rounds"])
+        assert obj == ref.objective and np.array_equal(a, ref.assign)
+        if ratio == 0:
+            assert st["dijkstra"] == 0
+        elif k <= 130:   # W in LDS: Dijkstra order is available
+            assert st["dijkstra"] > 0
+
+
+def test_set_option_rejects_bad_values(lb):
+    import torch
+    inst = L.random_small(k=5, n=50, seed=3)
+    with lb.Instance(torch.from_numpy(inst.cm).cuda(), inst.cap, inst.pen) as I:
+        for opt, val in ((lb.OPT_SEARCH_RATIO, -1), (lb.OPT_SEARCH_RATIO, (1 << 20) + 1), (99, 1)):
+            with pytest.raises(lb.LbddError) as e:
+                I.set_option(opt, val)
+            assert e.value.code == lb.E_INVAL
+
+
+def test_tune_search_records_ratio_and_stays_exact(lb):
+    """The tuner times five search ratios on a prefix; the fastest becomes the
+    default of new instances with that k, and the solve is unchanged."""
+    import torch
+    inst = L.random_small(k=29, n=6000, seed=29, cm_hi=500, pen_hi=400)
+    say("tune search", inst.name)
+    ratio, ms = lb.tune_search(torch.from_numpy(inst.cm).cuda(), inst.cap, inst.pen, iters=3000)
+    say("  ratio", ratio, "ms", ms)
+    assert len(ms) == 5 and all(t > 0 for t in ms)
+    assert ratio in (0, 32, 64, 128, 1 << 20)
+    ref = oracle.solve(*inst.arrays())
+    with lb.Instance(torch.from_numpy(inst.cm).cuda(), inst.cap, inst.pen) as I:
+        assert I.get_option(lb.OPT_SEARCH_RATIO) == ratio
+        I.solve()
+        assert I.objective() == ref.objective and np.array_equal(I.assignment(), ref.assign)
+
+
+@pytest.mark.parametrize("k,n", [(37, 20_000), (64, 50_000), (100, 100_000)])
+def test_tune_best_transfers_bit_exact(lb, k, n):
+    """Every tile configuration the tuner times gives the same table; the one
+    it keeps is used by later scans of the same k."""
+    import torch
+    rng = np.random.default_rng(k + n)
+    cm = rng.integers(0, 3000, size=(n, k), dtype=np.int64).astype(np.int32)
+    assign = rng.integers(-1, k, size=n).astype(np.int32)
+    rank = rng.permutation(n).astype(np.int32)
+    say("tune scan", k, n)
+    ref = oracle.best_transfers(cm, assign, rank.astype(np.int64))
+    cmd, ad, rd = (torch.from_numpy(x).cuda() for x in (cm, assign, rank))
+    W, cfg, ms, count = lb.tune_best_transfers(cmd, ad, rd, reps=2)
+    say("  config", cfg, "ms", ms, "candidates", count)
+    assert count >= 1
+    vec, lpr, np_, waves = cfg
+    assert vec in (1, 4) and lpr * np_ * vec >= k and waves in (1, 2)
+    assert np.array_equal(W.cpu().numpy().view(np.uint64), ref)
+    W2 = lb.best_transfers(cmd, ad, rd)
+    assert np.array_equal(W2.cpu().numpy().view(np.uint64), ref)
