@@ -14,6 +14,8 @@ Prints one JSON line.  Extra objects:
                 peak, timed with HIP events on the stream it runs on
   scan          the whole-matrix best-transfer scan at k=500, n=1,000,000
                 (2 GB of costs) against HBM peak
+  tune          what the autotuner chose before timing: the search choice
+                for k=100 (timed on a solve prefix) and the scan's tiles
   batch         batched launch vs plain solves on a subset of the batched
                 workload (solves/s, completion latency p50/p99)
   serve         request server vs plain FIFO on a Poisson trace (--serve N)
@@ -33,6 +35,26 @@ HBM_PEAK_GBS = 8000.0
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def recorded_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` on this benchmark's workload, from the
+    committed counter summary (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by
+    the factors a plain elementwise kernel of known size gave), or None when
+    the kernel's sources changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+            rec = json.load(f)[kernel]
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+    except (OSError, KeyError, ValueError):
+        return None
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return int(rec["fetch_bytes"]) + int(rec["write_bytes"])
 
 
 def solve_bytes(k: int, stats: dict) -> int:
@@ -147,6 +169,11 @@ def main():
                     help="requests of a Poisson trace to serve vs plain FIFO (0: skip)")
     ap.add_argument("--serve-max-n", type=int, default=200_000)
     ap.add_argument("--serve-max-k", type=int, default=256)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (search choice on a solve prefix, scan tiles)")
+    ap.add_argument("--tune-iters", type=int, default=0,
+                    help="iterations the search autotuner times per candidate (0: the whole solve; "
+                         "a short prefix has too few searches to tell the candidates apart)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -170,6 +197,18 @@ def main():
     torch.cuda.synchronize()
     with open(os.path.join(ROOT, "tests", "golden", "oracle_results.json")) as f:
         gold = json.load(f)["C2"]
+
+    tune = {}
+    if not args.no_tune:
+        # one-off per k, outside the timed region: later instances with this k
+        # start with the fastest search choice
+        titers = args.tune_iters if args.tune_iters > 0 else inst.n
+        log(f"bench: search autotuner, {titers} iterations per candidate")
+        ratio, cand_ms = lbdd.tune_search(cm, inst.cap, inst.pen, iters=titers, stream=stream)
+        tune["search"] = {"k": inst.k, "iters_per_candidate": titers, "chosen_ratio_x16": ratio,
+                          "candidates_ratio_x16": [0, 32, 64, 128, 1 << 20],
+                          "candidates_ms": [round(x, 3) for x in cand_ms]}
+        log(f"bench: search autotuner chose ratio {ratio} ({cand_ms} ms)")
 
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -206,7 +245,8 @@ def main():
     kern_s = float(np.mean(solve_ms)) / 1e3
     achieved = nbytes / kern_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": recorded_traffic("solve_kernel"),
                 "kernel": "solve_kernel", "bytes_per_launch": nbytes,
                 "launch_ms": round(kern_s * 1e3, 3)}
 
@@ -223,6 +263,14 @@ def main():
                            device=dev)
         lbdd.best_transfers(cmb, assign, rank, W, work, stream)
         torch.cuda.synchronize()
+        if not args.no_tune:
+            _, cfg, tms, ncfg = lbdd.tune_best_transfers(cmb, assign, rank, reps=3, W=W, work=work,
+                                                         stream=stream)
+            tune["scan"] = {"k": big.k, "n": big.n, "configs_timed": ncfg,
+                            "chosen": {"cols_per_load": cfg[0], "lanes_per_row": cfg[1],
+                                       "groups_per_lane": cfg[2], "waves": cfg[3]},
+                            "default_kernel_ms": round(tms[0], 4), "tuned_kernel_ms": round(tms[1], 4)}
+            log(f"bench: scan autotuner chose {cfg}: {tms[0]:.4f} -> {tms[1]:.4f} ms")
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -247,7 +295,8 @@ def main():
                 "unit": "GB/s", "frac": round(sbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                 "kernel_ms": round(ms_k, 4), "kernel_bytes": kbytes,
                 "kernel_achieved": round(kbytes / (ms_k / 1e3) / 1e9, 1),
-                "kernel_frac": round(kbytes / (ms_k / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+                "kernel_frac": round(kbytes / (ms_k / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                "kernel_traffic": recorded_traffic("scan_kernel")}
         log(f"bench: scan call {ms:.3f} ms -> {scan['achieved']} GB/s; scan kernel {ms_k:.3f} ms "
             f"-> {scan['kernel_achieved']} GB/s")
         del cmb, W, work
@@ -294,6 +343,7 @@ def main():
         "stats": stats,
         "roofline": roofline,
         "scan": scan,
+        "tune": tune or None,
         "batch": batch,
         "serve": serve,
         "cpu_baseline": cpu,

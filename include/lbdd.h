@@ -255,7 +255,9 @@ int lbdd_best_transfers(int32_t k, int64_t n, const int32_t *cm, const int32_t *
  * lbdd_create) once per candidate search ratio (0, 32, 64, 128, 2^20), times
  * its first `iters` iterations with HIP events on `hip_stream`, checks that
  * all candidates reach the same objective, and records the fastest ratio for
- * this k (used by later lbdd_create calls).  Writes it to *ratio_out and the
+ * this k (used by later lbdd_create calls) if it beats the default (64) by
+ * more than 2 %, else the default.  A short prefix has few searches: time
+ * enough iterations (up to n) to tell the candidates apart.  Writes it to *ratio_out and the
  * candidates' times in ms to ms_out[0 .. count-1].  Synchronises.  Returns
  * the number of candidates (5), or LBDD_E_INVAL, LBDD_E_NOMEM, LBDD_E_DEVICE,
  * LBDD_E_INTERNAL (candidates disagreed). */
@@ -268,7 +270,8 @@ int lbdd_tune_search(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap
  * configuration that covers k columns (lanes per row, column groups per
  * lane, one or two resident waves of workgroups) `reps` times after a
  * warm-up, checks on the device that each produced the default's table, and
- * records the fastest for this k and load width (16-byte loads need
+ * records the fastest (the default unless another is faster by more than
+ * 2 %) for this k and load width (16-byte loads need
  * k % 4 == 0 and a 16-byte aligned cm).  On return W holds the table of the
  * inputs and work their grouping, as after lbdd_best_transfers.
  *   config_out  [4] int32: columns per load, lanes per row, column groups per

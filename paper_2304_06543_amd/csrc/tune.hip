@@ -5,15 +5,15 @@
 //   Dijkstra order runs so when (deepest hop + 1) x ratio > k, i.e. when the
 //   Bellman-Ford rounds it would need cost more than k Dijkstra steps.  The
 //   ratio is the cost of one round in steps; it depends on k and the workload.
-//   The tuner solves a prefix of the caller's instance once per candidate
-//   ratio and keeps the fastest; instances created afterwards with the same k
+//   The tuner solves (a prefix of) the caller's instance once per candidate
+//   ratio and keeps the fastest, if it beats the default by more than 2 %; instances created afterwards with the same k
 //   start with it (lbdd_set_option overrides it per instance), and so do the
 //   instances of a batched launch, which read it from their own state.
 // * Scan tiles (lbdd_tune_best_transfers).  The whole-matrix scan can give a
 //   row 1 to 64 lanes, each lane 1 to 32 column groups, and run one or two
 //   resident waves of workgroups.  The tuner times every shape that fits k on
 //   the caller's inputs; later scans with the same k and load width use the
-//   fastest.
+//   fastest, if it beats the default by more than 2 %.
 // Every candidate computes the same bits (searches: the same labels,
 // predecessors and hops; the scan: keys reduced by an exact minimum), so the
 // tuned choice is a matter of time only.
@@ -41,6 +41,9 @@ int64_t tuned_search_ratio(int32_t k) {
 
 namespace {
 using lbdd::fail;
+
+// a candidate replaces the default only if it is faster by more than 2 %
+constexpr float NOISE = 0.98f;
 
 int hip_err(hipError_t e, const char *what) {
   return fail(e == hipErrorOutOfMemory ? LBDD_E_NOMEM : LBDD_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
@@ -74,8 +77,7 @@ int lbdd_tune_search(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   Timer tm;
   if (hipError_t e = tm.init(); e != hipSuccess) return hip_err(e, "hipEventCreate");
-  int best = 0;
-  float best_ms = 0.f;
+  float times[NC] = {};
   int64_t obj0 = 0;
   for (int c = 0; c < NC; ++c) {
     lbdd_instance *h = nullptr;
@@ -98,8 +100,14 @@ int lbdd_tune_search(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap
     else if (obj != obj0)   // every candidate computes the same allotment
       return fail(LBDD_E_INTERNAL, "search ratio %lld changed the objective", (long long)CAND[c]);
     if (c < count) ms_out[c] = ms;
-    if (c == 0 || ms < best_ms) { best = c; best_ms = ms; }
+    times[c] = ms;
   }
+  // the default stays unless a candidate is faster by more than the noise
+  int best = 0;
+  while (CAND[best] != lbdd::DEFAULT_SEARCH_RATIO) ++best;
+  const float base = times[best];
+  for (int c = 0; c < NC; ++c)
+    if (times[c] < NOISE * base && times[c] < times[best]) best = c;
   {
     std::lock_guard<std::mutex> g(lbdd::g_mu);
     lbdd::g_ratio[k] = CAND[best];
@@ -165,8 +173,8 @@ int lbdd_tune_best_transfers(int32_t k, int64_t n, const int32_t *cm, const int3
                           : lbdd::launch_differ(ref, W, kk, flag, st);
     if (e != hipSuccess) return hip_err(e, "checking a scan configuration");
     const float ms = total / reps;
-    if (c == 0) default_ms = ms;
-    if (c == 0 || ms < best_ms) { best = c; best_ms = ms; }
+    if (c == 0) default_ms = best_ms = ms;   // candidate 0 is the default
+    else if (ms < NOISE * default_ms && ms < best_ms) { best = c; best_ms = ms; }
   }
   int32_t differ = 0;
   hipError_t e0 = hipMemcpyAsync(&differ, flag, 4, hipMemcpyDeviceToHost, st);
