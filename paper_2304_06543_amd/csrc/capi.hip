@@ -56,7 +56,7 @@ void release(lbdd_instance *h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->st);
   void *ptrs[] = {h->cm, h->smin, h->cap, h->pen, h->assign, h->load, h->members,
-                  h->slot, h->unperm, h->order, h->scalars, h->W, h->best, h->meta, h->thr};
+                  h->slot, h->unperm, h->order, h->scalars, h->W, h->Wh, h->best, h->meta, h->thr};
   for (void *p : ptrs)
     if (p) (void)hipFreeAsync(p, h->st);
   (void)hipStreamSynchronize(h->st);
@@ -130,6 +130,7 @@ int lbdd_create(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity
   if (e == hipSuccess) e = dalloc(&h->order, (size_t)n, h->st);
   if (e == hipSuccess) e = dalloc(&h->scalars, (size_t)lbdd::SC_COUNT, h->st);
   if (e == hipSuccess) e = dalloc(&h->W, (size_t)k * k, h->st);
+  if (e == hipSuccess) e = dalloc(&h->Wh, (size_t)k * k, h->st);
   if (e == hipSuccess) e = dalloc(&h->best, (size_t)k * k * lbdd::BEST_M, h->st);
   if (e == hipSuccess) e = dalloc(&h->meta, (size_t)k * k, h->st);
   if (e == hipSuccess) e = dalloc(&h->thr, (size_t)k * k, h->st);

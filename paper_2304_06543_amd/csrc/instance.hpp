@@ -25,6 +25,7 @@ struct lbdd_instance {
   int32_t *unperm = nullptr;            // [n] staging for lbdd_assignment
   int64_t *order = nullptr, *scalars = nullptr;
   uint64_t *W = nullptr;
+  uint32_t *Wh = nullptr;
   uint64_t *best = nullptr;
   uint8_t *meta = nullptr;
   uint64_t *thr = nullptr;
@@ -32,7 +33,7 @@ struct lbdd_instance {
   lbdd::InstView view() const {
     lbdd::InstView v;
     v.k = k; v.n = n; v.cm = cm; v.smin = smin; v.cap = cap; v.pen = pen;
-    v.assign = assign; v.load = load; v.members = members; v.slot = slot; v.W = W;
+    v.assign = assign; v.load = load; v.members = members; v.slot = slot; v.W = W; v.Wh = Wh;
     v.best = best; v.meta = meta; v.thr = thr;
     v.scalars = scalars;
     return v;

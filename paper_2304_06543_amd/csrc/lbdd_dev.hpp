@@ -49,6 +49,9 @@ struct InstView {
   int32_t *members;        // [k][n] rows allotted to each center (first load[u])
   int32_t *slot;           // [n] index of row r in its center's member list
   uint64_t *W;             // [k][k] best-transfer table (heads of the lists below)
+  uint32_t *Wh;            // [k][k] high words of W (delta + 2^31, all ones = no
+                           // transfer): what a search reads, at half the bytes,
+                           // while W is in global memory
   uint64_t *best;          // [k][k][BEST_M] smallest transfer keys of each pair
   uint8_t *meta;           // [k][k] keys held (low 4 bits), every unit held (META_ALL)
   uint64_t *thr;           // [k][k] a joining unit's key changes the list (or its

@@ -69,12 +69,13 @@ struct AdmissionQueue {
 
 // Device memory an instance of k centers and n units holds while it is being
 // solved: the permuted cost matrix and the per-center member lists (4nk each),
-// per-unit arrays, the k x k table and the k x k x 8 best-transfer lists,
+// per-unit arrays, the k x k table (with its high words) and the k x k x 8
+// best-transfer lists,
 // plus the transient setup buffers (the
 // unpermuted cost matrix copy and sort keys).
 inline size_t instance_footprint(int32_t k, int64_t n) {
   const size_t nk = (size_t)n * (size_t)k;
-  return nk * 4 * 3 + (size_t)n * (4 * 4 + 8 + 4 + 16) + (size_t)k * k * (8 + 8 * 8 + 1 + 8) +
+  return nk * 4 * 3 + (size_t)n * (4 * 4 + 8 + 4 + 16) + (size_t)k * k * (8 + 4 + 8 * 8 + 1 + 8) +
          (size_t)k * 16 + 4096;
 }
 

@@ -47,6 +47,7 @@ __device__ inline int lanes_below(uint64_t mask) {
 
 struct Lds {
   uint64_t *W;      // [k][k] (LDS copy or the global table)
+  uint32_t *wh;     // global high words of W while W is global, else null
   uint64_t *red;    // [k+1] per-target minimum
   int64_t *dist;    // [k+1]
   int32_t *pred;    // [k+1]
@@ -65,6 +66,12 @@ struct Lds {
   int32_t *trow;    // [k+1] columns to refill
   uint64_t *wmin;   // [2][NT/64] per-wavefront minima of a refill round
 };
+
+// W[idx] = key, and its high word when W is global
+__device__ inline void set_w(const Lds &L, int64_t idx, uint64_t key) {
+  L.W[idx] = key;
+  if (L.wh) L.wh[idx] = (uint32_t)(key >> 32);
+}
 
 struct Scalars {
   int64_t obj;
@@ -173,7 +180,7 @@ __device__ __forceinline__ int join_center(const InstView &I, const Lds &L, int 
     I.meta[idx] = (uint8_t)(c2 | (all2 ? META_ALL : 0));
     I.thr[idx] = list_threshold(a, c2, all2);
     if (a[0] < L.W[idx]) {
-      L.W[idx] = a[0];
+      set_w(L, idx, a[0]);
       changed = 1;
       breaks |= L.pot[v] + delta < L.pot[w];
     }
@@ -207,7 +214,7 @@ __device__ __forceinline__ void leave_center(const InstView &I, const Lds &L, in
     list_store(I.best + idx * BEST_M, a);
     I.meta[idx] = (uint8_t)((c - 1) | (meta & META_ALL));
     I.thr[idx] = list_threshold(a, c - 1, meta & META_ALL);
-    L.W[idx] = a[0];                             // stale if unknown; refill sets it
+    set_w(L, idx, a[0]);                         // stale if unknown; refill sets it
   }
   __syncthreads();
 }
@@ -269,7 +276,7 @@ __device__ __forceinline__ void refill_column(const InstView &I, const Lds &L, S
     for (int j = 0; j < BEST_M; ++j) c += out[j] != KEY_NONE;
     I.meta[idx] = (uint8_t)(c | (m <= BEST_M ? META_ALL : 0));
     I.thr[idx] = list_threshold(out, c, m <= BEST_M);
-    L.W[idx] = out[0];
+    set_w(L, idx, out[0]);
     S.stats[ST_ROWS_SCANNED] += m;
     S.stats[ST_REFILLS] += 1;
   }
@@ -353,10 +360,14 @@ __device__ __forceinline__ void retry_potential(const InstView &I, const Lds &L,
 // ((label + DIST_BIAS) << 16) | u, so relaxing a transfer edge is one add of
 // delta << 16; only the key's high word (delta + 2^31, all ones = no edge) is
 // read.  Returns false (and sets the status) on a change in round k+1.
+template <bool WLDS>
 __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Scalars &S, int s) {
   const int k = I.k;
   const int tid = threadIdx.x;
-  const uint32_t *Whi = reinterpret_cast<const uint32_t *>(L.W) + 1;   // high word of W[i]: Whi[2i]
+  // high word of W[i]: Whi[WS * i] (in the LDS copy of W, or the packed
+  // global array next to the global W)
+  constexpr int WS = WLDS ? 2 : 1;
+  const uint32_t *Whi = WLDS ? reinterpret_cast<const uint32_t *>(L.W) + 1 : L.wh;
   for (int v = tid; v <= k; v += NT) {
     L.dist[v] = (v == s) ? 0 : DIST_NONE;
     L.pred[v] = -1;
@@ -383,25 +394,28 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
     const int32_t *F = cur ? L.front1 : L.front0;
     const uint64_t *FB = cur ? L.fbase1 : L.fbase0;
     // candidate of target v over frontier entries j = j0, j0+G, ... in
-    // batches of four: all loads of a batch are in flight together
+    // batches of B: all loads of a batch are in flight together (batches of
+    // 8 or 16 did not help with the high words in L2 either: at k = 500 a
+    // round is bound by the arithmetic of nf x k relaxations on one CU)
+    constexpr int B = 4;
     auto relax_target = [&](int v, int j0) -> uint64_t {
       uint64_t best = KEY_NONE;
-      for (int j = j0; j < nf; j += 4 * G) {
-        int32_t off[4];
-        uint64_t b[4];
-        bool ok[4];
+      for (int j = j0; j < nf; j += B * G) {
+        int32_t off[B];
+        uint64_t b[B];
+        bool ok[B];
 #pragma unroll
-        for (int x = 0; x < 4; ++x) {
+        for (int x = 0; x < B; ++x) {
           const int jj = j + x * G;
           ok[x] = jj < nf;
           off[x] = F[ok[x] ? jj : j];
           b[x] = FB[ok[x] ? jj : j];
         }
-        uint32_t hi[4];
+        uint32_t hi[B];
 #pragma unroll
-        for (int x = 0; x < 4; ++x) hi[x] = Whi[2 * ((int64_t)off[x] + v)];
+        for (int x = 0; x < B; ++x) hi[x] = Whi[WS * ((int64_t)off[x] + v)];
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
+        for (int x = 0; x < B; ++x)
           if (ok[x] && hi[x] != 0xffffffffu)
             best = umin(best, b[x] + ((uint64_t)(int64_t)(int32_t)(hi[x] - 0x80000000u) << 16));
       }
@@ -672,7 +686,7 @@ __device__ __forceinline__ bool refine(const InstView &I, const Lds &L, Scalars 
     if (tid == 0) S.depth += ((S.maxhop + 1) * 16 - S.depth) / 8;
     sin_from_labels(I, L, s, mode);
   } else {
-    if (!bellman_ford(I, L, S, s)) return false;
+    if (!bellman_ford<WLDS>(I, L, S, s)) return false;
     sin_from_labels(I, L, s, mode);
   }
   const int64_t D = L.dist[k];
@@ -746,6 +760,7 @@ __device__ __forceinline__ Lds carve_lds(const InstView &I, unsigned char *lds) 
   unsigned char *p = lds;
   if (WLDS) { L.W = reinterpret_cast<uint64_t *>(p); p += (size_t)k * k * 8; }
   else L.W = I.W;
+  L.wh = WLDS ? nullptr : I.Wh;
   L.red = reinterpret_cast<uint64_t *>(p); p += (size_t)K1 * 8;
   L.dist = reinterpret_cast<int64_t *>(p); p += (size_t)K1 * 8;
   L.pred = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
@@ -778,6 +793,8 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
 
   if (WLDS)
     for (int64_t i = tid; i < (int64_t)k * k; i += NT) L.W[i] = I.W[i];
+  else   // a launch that kept W in LDS left the high words behind
+    for (int64_t i = tid; i < (int64_t)k * k; i += NT) L.wh[i] = (uint32_t)(I.W[i] >> 32);
   for (int i = tid; i < k; i += NT) L.pot[i] = 0;
   for (int i = tid; i < k; i += NT) { L.load[i] = I.load[i]; L.cap[i] = I.cap[i]; L.pen[i] = I.pen[i]; }
   if (tid == 0) {
@@ -888,6 +905,7 @@ __global__ void init_state_kernel(InstView I) {
   for (int64_t i = t0; i < I.n; i += stride) I.assign[i] = -1;
   for (int64_t i = t0; i < (int64_t)I.k * I.k; i += stride) {
     I.W[i] = KEY_NONE;
+    I.Wh[i] = 0xffffffffu;
     I.meta[i] = META_ALL;                       // empty center: every unit (none) held
     I.thr[i] = KEY_NONE;                        // ... so every joining unit enters
   }
