@@ -181,8 +181,10 @@ enum { LBDD_JOB_QUEUED = 0, LBDD_JOB_RUNNING = 1, LBDD_JOB_DONE = 2 };
 
 /* hbm_budget: bytes of device memory jobs may hold at once (> 0);
  * max_jobs: job slots (>= 1); reserve_cus: compute units left free for the
- * setup kernels of newly admitted jobs.  Errors: LBDD_E_INVAL, LBDD_E_NOMEM,
- * LBDD_E_DEVICE. */
+ * setup kernels of newly admitted jobs.  On MI355X (256 CUs) leave at least
+ * 64: with more than ~192 resident workers, other kernels (the admissions'
+ * setup) are held back until idle workers leave, and the pool shrinks to the
+ * busy ones.  Errors: LBDD_E_INVAL, LBDD_E_NOMEM, LBDD_E_DEVICE. */
 int lbdd_server_create(size_t hbm_budget, int32_t max_jobs, int32_t reserve_cus, lbdd_server **out);
 
 /* Queue one instance (arguments as lbdd_create with a host cost matrix).
@@ -201,8 +203,10 @@ int lbdd_server_poll(lbdd_server *srv, uint64_t ticket, int32_t *state, int64_t 
 int lbdd_server_wait(lbdd_server *srv, uint64_t ticket, int64_t *objective);
 
 /* Copy a finished job's allotment (n int32, host memory; may be NULL) and its
- * times in seconds since the server started: times[0] submitted, [1] admitted
- * (on the device and published to the workers), [2] finished (may be NULL).
+ * times (5 doubles, may be NULL): in seconds since the server started, [0]
+ * submitted, [1] admitted (on the device and published to the workers), [2]
+ * seen finished by the server; in seconds of the device clock, [3] when its
+ * first iteration began and [4] when its last one ended on the device.
  * Releases the ticket.  Errors: LBDD_E_INVAL (unknown ticket), LBDD_E_STATE
  * (not finished), or the job's own error. */
 int lbdd_server_result(lbdd_server *srv, uint64_t ticket, int32_t *assign, double *times);

@@ -111,6 +111,15 @@ struct ServiceCtl {
   int64_t published;        // jobs published so far (host writes, release)
   int64_t shutdown;         // nonzero: workers leave once no job is waiting
 };
+// Device-memory side of the service kernel: the claim counter and mirrors of
+// the host's control block.  Idle workers poll these (in L2) instead of host
+// memory; one worker at a time refreshes the mirrors from host memory.
+struct ServiceDev {
+  int64_t head;             // jobs claimed so far
+  int64_t published;        // mirror of ServiceCtl::published
+  int64_t shutdown;         // mirror of ServiceCtl::shutdown
+  int64_t polled;           // device timer of the last refresh from host memory
+};
 struct ServiceJob {
   InstView inst;            // device state of the job's instance
 };
@@ -132,7 +141,7 @@ hipError_t launch_solve_batch(const BatchItem *items_dev, int32_t m, int32_t *he
                               int workers, hipStream_t st);
 int device_cus();
 hipError_t launch_service(ServiceCtl *ctl, const ServiceJob *ring, int32_t ring_size, int64_t *done,
-                          int64_t *head, int64_t idle_ticks, int workers, hipStream_t st);
+                          ServiceDev *dev, int64_t idle_ticks, int workers, hipStream_t st);
 // tune.hip: values chosen by the autotuner for this process
 int64_t tuned_search_ratio(int32_t k);
 // scan.hip: whole-matrix best-transfer table.  A tile configuration: VEC

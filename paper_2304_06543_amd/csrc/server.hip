@@ -51,6 +51,7 @@ struct Job {
   int64_t objective = 0;
   std::vector<int32_t> assign;
   double t_submit = 0, t_admit = 0, t_done = 0;
+  double t_dev0 = 0, t_dev1 = 0;               // device clock: first and last iteration
 };
 
 }  // namespace
@@ -67,7 +68,7 @@ struct lbdd_server {
   lbdd::ServiceCtl *ctl_d = nullptr; // the same three, device view
   lbdd::ServiceJob *ring_d = nullptr;
   int64_t *done_d = nullptr;
-  int64_t *head = nullptr;           // device
+  lbdd::ServiceDev *dev = nullptr;   // device: claim counter and control mirrors
   hipEvent_t kernel_end = nullptr;
   bool kernel_launched = false;
 
@@ -86,7 +87,7 @@ struct lbdd_server {
 
   int ensure_kernel() {
     if (kernel_launched && hipEventQuery(kernel_end) == hipErrorNotReady) return LBDD_OK;
-    hipError_t e = lbdd::launch_service(ctl_d, ring_d, ring_size, done_d, head, IDLE_TICKS, workers, run_st);
+    hipError_t e = lbdd::launch_service(ctl_d, ring_d, ring_size, done_d, dev, IDLE_TICKS, workers, run_st);
     if (e == hipSuccess) e = hipEventRecord(kernel_end, run_st);
     if (e != hipSuccess) return lbdd::fail(LBDD_E_DEVICE, "service kernel launch: %s", hipGetErrorString(e));
     kernel_launched = true;
@@ -147,6 +148,11 @@ void lbdd_server::loop() {
       std::vector<int32_t> a((size_t)j.n);
       int rc = lbdd_objective(inst, &obj);
       if (rc == LBDD_OK) rc = lbdd_assignment(inst, a.data(), 0);
+      int64_t st[21] = {0};
+      if (rc == LBDD_OK && lbdd_stats(inst, st, 21) == 21 && st[20] > 0) {
+        j.t_dev0 = (double)st[14] / ((double)st[20] * 1e3);
+        j.t_dev1 = (double)st[15] / ((double)st[20] * 1e3);
+      }
       lbdd_destroy(inst);
       lk.lock();
       j.inst = nullptr;
@@ -207,9 +213,9 @@ int lbdd_server_create(size_t hbm_budget, int32_t max_jobs, int32_t reserve_cus,
   if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->ctl_d), s->ctl, 0);
   if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->ring_d), s->ring, 0);
   if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->done_d), s->done, 0);
-  if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void **>(&s->head), sizeof(int64_t), s->adm_st);
-  int64_t zero = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(s->head, &zero, sizeof zero, hipMemcpyHostToDevice, s->adm_st);
+  if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void **>(&s->dev), sizeof(lbdd::ServiceDev), s->adm_st);
+  const lbdd::ServiceDev zero{};
+  if (e == hipSuccess) e = hipMemcpyAsync(s->dev, &zero, sizeof zero, hipMemcpyHostToDevice, s->adm_st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->adm_st);
   if (e != hipSuccess) {
     lbdd_server_destroy(s);
@@ -278,7 +284,10 @@ int lbdd_server_result(lbdd_server *s, uint64_t ticket, int32_t *assign, double 
   if (j.state == LBDD_JOB_QUEUED || j.state == LBDD_JOB_RUNNING) return lbdd::fail(LBDD_E_STATE, "job not finished");
   const int st = j.state;
   if (st == LBDD_JOB_DONE && assign) memcpy(assign, j.assign.data(), sizeof(int32_t) * (size_t)j.n);
-  if (times) { times[0] = j.t_submit; times[1] = j.t_admit; times[2] = j.t_done; }
+  if (times) {
+    times[0] = j.t_submit; times[1] = j.t_admit; times[2] = j.t_done;
+    times[3] = j.t_dev0; times[4] = j.t_dev1;
+  }
   s->jobs.erase(it);
   return st == LBDD_JOB_DONE ? LBDD_OK : lbdd::fail(st, "job failed");
 }
@@ -310,7 +319,7 @@ void lbdd_server_destroy(lbdd_server *s) {
   }
   if (s->ctl) __atomic_store_n(&s->ctl->shutdown, 1, __ATOMIC_RELEASE);
   if (s->run_st) (void)hipStreamSynchronize(s->run_st);
-  if (s->head) (void)hipFreeAsync(s->head, s->adm_st);
+  if (s->dev) (void)hipFreeAsync(s->dev, s->adm_st);
   if (s->adm_st) (void)hipStreamSynchronize(s->adm_st);
   if (s->ctl) (void)hipHostFree(s->ctl);
   if (s->ring) (void)hipHostFree(s->ring);

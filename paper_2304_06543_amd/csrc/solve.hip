@@ -953,35 +953,61 @@ namespace {
 // its descriptor from pinned host memory, solves it, and signals completion
 // with a system-scope release store into pinned memory (so the host also sees
 // the job's results in device memory).  A worker leaves when shutdown is
-// requested or after idle_ticks of device time without a job; the host
-// launches the kernel again when new work arrives.
+// requested or after idle_ticks of device time in which it took no job and no
+// job was published; the host launches the kernel again when new work arrives
+// after all workers left.
 __global__ __launch_bounds__(NT) void service_kernel(ServiceCtl *ctl, const ServiceJob *ring,
-                                                     int32_t ring_size, int64_t *done, int64_t *head,
+                                                     int32_t ring_size, int64_t *done, ServiceDev *dev,
                                                      uint32_t lds_avail, int64_t idle_ticks) {
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ Scalars S;
   __shared__ int64_t claim;
   constexpr int WORDS = sizeof(InstView) / 4;
   __shared__ uint32_t job[WORDS];
+  constexpr int64_t POLL_TICKS = 200;          // 2 us of the 100 MHz device timer
   for (;;) {
     __syncthreads();                           // previous job fully written back
     if (threadIdx.x == 0) {
       int64_t got = -1;
-      const int64_t t0 = now();
+      int64_t t0 = now();
+      int64_t seen = -1;
       for (;;) {
-        const int64_t pub = __hip_atomic_load(&ctl->published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-        int64_t h = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // at most one worker every POLL_TICKS reads the host's control block
+        // (a flood of reads over PCIe from idle workers would starve the
+        // command processor's own fetches of queue packets) and mirrors it
+        const int64_t t = now();
+        int64_t last = __hip_atomic_load(&dev->polled, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t - last > POLL_TICKS &&
+            __hip_atomic_compare_exchange_strong(&dev->polled, &last, t, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)) {
+          const int64_t p = __hip_atomic_load(&ctl->published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+          const int64_t q = __hip_atomic_load(&ctl->shutdown, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          __hip_atomic_fetch_max(&dev->published, p, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          if (q) __hip_atomic_store(&dev->shutdown, q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // read-modify-writes are performed where the line is coherent for the
+        // whole device; a plain load could keep hitting a stale copy in this
+        // XCD's L2
+        const int64_t pub = __hip_atomic_fetch_add(&dev->published, (int64_t)0, __ATOMIC_ACQUIRE,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        // the idle clock restarts whenever a job is published: while requests
+        // keep arriving the whole pool stays, even if others take them
+        if (pub != seen) { seen = pub; t0 = now(); }
+        int64_t h = __hip_atomic_fetch_add(&dev->head, (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (h < pub) {
-          if (__hip_atomic_compare_exchange_strong(head, &h, h + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+          if (__hip_atomic_compare_exchange_strong(&dev->head, &h, h + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT)) {
             got = h;
             break;
           }
-          continue;
+          continue;                              // another worker took job h: try the next one
         }
-        if (__hip_atomic_load(&ctl->shutdown, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+        if (__hip_atomic_fetch_add(&dev->shutdown, (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         if (now() - t0 > idle_ticks) break;
-        __builtin_amdgcn_s_sleep(64);
+        // ~25 us between polls: hundreds of workers polling faster hold up
+        // the launch of other kernels on the device
+#pragma unroll
+        for (int z = 0; z < 8; ++z) __builtin_amdgcn_s_sleep(127);
       }
       claim = got;
       if (got >= 0) {
@@ -1016,12 +1042,12 @@ int device_cus() {
 }
 
 hipError_t launch_service(ServiceCtl *ctl, const ServiceJob *ring, int32_t ring_size, int64_t *done,
-                          int64_t *head, int64_t idle_ticks, int workers, hipStream_t st) {
+                          ServiceDev *dev, int64_t idle_ticks, int workers, hipStream_t st) {
   const size_t lds = LDS_BUDGET;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&service_kernel),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  service_kernel<<<workers, NT, lds, st>>>(ctl, ring, ring_size, done, head, (uint32_t)lds, idle_ticks);
+  service_kernel<<<workers, NT, lds, st>>>(ctl, ring, ring_size, done, dev, (uint32_t)lds, idle_ticks);
   return hipGetLastError();
 }
 

@@ -312,7 +312,7 @@ class Server:
     submit() keeps a reference to the cost matrix until the job's result has
     been taken with result()."""
 
-    def __init__(self, hbm_budget: int = 64 << 30, max_jobs: int = 1024, reserve_cus: int = 16):
+    def __init__(self, hbm_budget: int = 64 << 30, max_jobs: int = 1024, reserve_cus: int = 64):
         self._lib = load()
         self._s = C.c_void_p()
         _check(self._lib.lbdd_server_create(int(hbm_budget), int(max_jobs), int(reserve_cus),
@@ -343,10 +343,11 @@ class Server:
         return obj.value
 
     def result(self, ticket: int):
-        """(allotment int32[n], times (submitted, admitted, finished) in s)."""
+        """(allotment int32[n], times): submitted, admitted, finished in s since
+        the server started; device clock at the first and the last iteration."""
         _, n = self._keep[ticket]
         a = np.empty(n, np.int32)
-        times = np.zeros(3, np.float64)
+        times = np.zeros(5, np.float64)
         try:
             _check(self._lib.lbdd_server_result(self._s, int(ticket), a.ctypes.data_as(C.c_void_p),
                                                 times.ctypes.data_as(C.c_void_p)))

@@ -56,6 +56,27 @@ def test_results_in_the_mix_equal_alone(lb):
         assert st["finished"] == len(insts) and st["failed"] == 0
 
 
+def test_jobs_submitted_together_run_side_by_side(lb):
+    """Jobs submitted together are solved concurrently by different workers:
+    their device intervals overlap, and the whole set takes far less than the
+    sum of the jobs' own device times.  (A pool that shrinks to the workers
+    that are busy would solve them one after another.)"""
+    insts = [L.gmm_manhattan(64, 30000, seed=300 + i, cap_frac=0.95, pen_lo=100, pen_hi=1000)
+             for i in range(8)]
+    with lb.Server(hbm_budget=8 << 30, max_jobs=16) as srv:
+        tickets = [srv.submit(*i.arrays()) for i in insts]
+        spans = []
+        for t in tickets:
+            srv.wait(t)
+            _, times = srv.result(t)
+            spans.append((times[3], times[4]))
+    say("device intervals", [(round(a, 3), round(b, 3)) for a, b in spans])
+    assert all(b > a for a, b in spans)
+    assert max(a for a, _ in spans) < min(b for _, b in spans)
+    whole = max(b for _, b in spans) - min(a for a, _ in spans)
+    assert whole < 0.5 * sum(b - a for a, b in spans)
+
+
 def test_tiny_budget_runs_one_at_a_time(lb):
     insts = mixed(6, 2)
     with lb.Server(hbm_budget=1, max_jobs=8) as srv:
