@@ -77,10 +77,12 @@ def run_batch(m, lbdd, L, torch, dev):
     log(f"bench: batch of {m}: plain solves one after another")
     t0 = time.perf_counter()
     plain_obj = []
-    for c, i in zip(cms, insts):
+    for j, (c, i) in enumerate(zip(cms, insts)):
         with lbdd.Instance(c, i.cap, i.pen) as h:
             h.solve()
             plain_obj.append(h.objective())
+        if (j + 1) % 16 == 0:
+            log(f"bench: batch: {j + 1} plain solves, {time.perf_counter() - t0:.1f} s")
     seq_s = time.perf_counter() - t0
     log(f"bench: batch of {m}: one batched launch")
     hs = [lbdd.Instance(c, i.cap, i.pen) for c, i in zip(cms, insts)]

@@ -25,15 +25,9 @@ __device__ __host__ inline int32_t key_delta(uint64_t key) {
 }
 __device__ __host__ inline uint32_t key_rank(uint64_t key) { return (uint32_t)key; }
 
-// Bellman-Ford candidate packed with its predecessor node so that one unsigned
-// min gives the smallest label and, among equal labels, the smallest node.
-// Labels are sums of at most LBDD_MAX_K+1 edges of magnitude < 2^31.
+// Bias that makes a search label (a sum of at most LBDD_MAX_K+1 edges of
+// magnitude < 2^31) non-negative, so labels order as unsigned integers.
 constexpr int64_t DIST_BIAS = 1ll << 46;
-__device__ inline uint64_t pack_cand(int64_t dist, int32_t node) {
-  return (uint64_t)(dist + DIST_BIAS) << 16 | (uint32_t)node;
-}
-__device__ inline int64_t cand_dist(uint64_t c) { return (int64_t)(c >> 16) - DIST_BIAS; }
-__device__ inline int32_t cand_node(uint64_t c) { return (int32_t)(c & 0xffffu); }
 
 // Device view of one instance.  Rows of `cm` are in processing order: row r is
 // the unit processed in iteration r, so a best-transfer key's rank is the row.

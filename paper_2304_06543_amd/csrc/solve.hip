@@ -351,15 +351,33 @@ __device__ __forceinline__ void retry_potential(const InstView &I, const Lds &L,
   __syncthreads();
 }
 
+// Label of a center during a search, packed so that one unsigned min orders
+// by (distance, edges, predecessor): ((dist + 2^41) << 22) | (edges << 11) |
+// pred.  Simple paths have at most k - 1 <= 2047 edges of |delta| < 2^30, so
+// |dist| < 2^41 and both small fields fit (a candidate one edge longer than
+// a simple path through all centers can carry into the distance field, which
+// only makes it larger: it is a cyclic walk and never improves a label).
+constexpr int64_t LAB_BIAS = 1ll << 41;
+__device__ inline uint64_t lab_pack(int64_t dist, int32_t edges, int32_t pred) {
+  return (uint64_t)(dist + LAB_BIAS) << 22 | (uint64_t)edges << 11 | (uint32_t)pred;
+}
+
 // Bellman-Ford from node s over the centers of the split graph; leaves the
 // center labels dist/pred/hop in LDS (s_in follows with sin_from_labels: it
-// has no out-edges, so it never changes a center's label).  Two barriers per
-// round: relax (frontier sources -> per-target minimum), then update (strict
-// improvement, next frontier, reset of the minima).  A frontier entry holds
-// the row offset u*k of its center and the packed candidate base
-// ((label + DIST_BIAS) << 16) | u, so relaxing a transfer edge is one add of
-// delta << 16; only the key's high word (delta + 2^31, all ones = no edge) is
-// read.  Returns false (and sets the status) on a change in round k+1.
+// has no out-edges, so it never changes a center's label).
+// The rounds relax edges out of the centers whose label changed, reading the
+// sources' current labels (not those of the previous round) and lowering the
+// targets' packed labels with LDS atomic minima.  The packed order is the tie
+// rule of synchronous rounds: the label a center ends with is the smallest
+// (distance, edges), i.e. its shortest distance and the round in which
+// synchronous rounds fix it, and its predecessor the smallest center reaching
+// it so; with no negative cycle this least fixpoint does not depend on the
+// order of the relaxations, and it is reached in at most as many rounds as
+// synchronous rounds need, since every label is at least as good after each
+// round.  Two barriers per round: relax, then collect the next frontier.  A
+// frontier entry holds the center and its row offset u*k; only the key's high
+// word of W (delta + 2^31, all ones = no edge) is read.  Returns false (and
+// sets the status) on a change in round k+1.
 template <bool WLDS>
 __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Scalars &S, int s) {
   const int k = I.k;
@@ -368,17 +386,17 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
   // global array next to the global W)
   constexpr int WS = WLDS ? 2 : 1;
   const uint32_t *Whi = WLDS ? reinterpret_cast<const uint32_t *>(L.W) + 1 : L.wh;
+  uint64_t *lab = L.red;                      // packed labels
+  int32_t *chg = L.hop;                       // changed in this round
   for (int v = tid; v <= k; v += NT) {
-    L.dist[v] = (v == s) ? 0 : DIST_NONE;
-    L.pred[v] = -1;
-    L.hop[v] = (v == s) ? 0 : -1;
-    L.red[v] = KEY_NONE;
+    lab[v] = (v == s) ? lab_pack(0, 0, 0) : KEY_NONE;
+    chg[v] = 0;
   }
   if (tid == 0) {
     S.nfront[0] = 1;
     S.nfront[1] = 0;
-    L.front0[0] = s * k;
-    L.fbase0[0] = pack_cand(0, s);
+    L.front0[0] = s;
+    reinterpret_cast<int32_t *>(L.fbase0)[0] = s * k;
   }
   __syncthreads();
   // target v of this thread and its share g of the frontier (k <= NT: every
@@ -392,60 +410,52 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
   for (int t = 1; t <= k + 1; ++t) {
     const int nf = S.nfront[cur];
     const int32_t *F = cur ? L.front1 : L.front0;
-    const uint64_t *FB = cur ? L.fbase1 : L.fbase0;
+    const int32_t *FO = reinterpret_cast<const int32_t *>(cur ? L.fbase1 : L.fbase0);
     // candidate of target v over frontier entries j = j0, j0+G, ... in
-    // batches of B: all loads of a batch are in flight together (batches of
-    // 8 or 16 did not help with the high words in L2 either: at k = 500 a
-    // round is bound by the arithmetic of nf x k relaxations on one CU)
+    // batches of four: all loads of a batch are in flight together
     constexpr int B = 4;
-    auto relax_target = [&](int v, int j0) -> uint64_t {
+    auto relax_target = [&](int v, int j0) {
       uint64_t best = KEY_NONE;
       for (int j = j0; j < nf; j += B * G) {
-        int32_t off[B];
-        uint64_t b[B];
+        int32_t u[B], off[B];
         bool ok[B];
 #pragma unroll
         for (int x = 0; x < B; ++x) {
           const int jj = j + x * G;
           ok[x] = jj < nf;
-          off[x] = F[ok[x] ? jj : j];
-          b[x] = FB[ok[x] ? jj : j];
+          u[x] = F[ok[x] ? jj : j];
+          off[x] = FO[ok[x] ? jj : j];
         }
+        uint64_t lu[B];
         uint32_t hi[B];
 #pragma unroll
-        for (int x = 0; x < B; ++x) hi[x] = Whi[WS * ((int64_t)off[x] + v)];
+        for (int x = 0; x < B; ++x) {
+          lu[x] = lab[u[x]];
+          hi[x] = Whi[WS * ((int64_t)off[x] + v)];
+        }
 #pragma unroll
         for (int x = 0; x < B; ++x)
           if (ok[x] && hi[x] != 0xffffffffu)
-            best = umin(best, b[x] + ((uint64_t)(int64_t)(int32_t)(hi[x] - 0x80000000u) << 16));
+            best = umin(best, (lu[x] & ~(uint64_t)0x7ff) +
+                                  ((uint64_t)(int64_t)(int32_t)(hi[x] - 0x80000000u) << 22) +
+                                  (1ull << 11) + (uint32_t)u[x]);
       }
-      return best;
+      if (best != KEY_NONE && best < atomicMin((unsigned long long *)&lab[v], (unsigned long long)best))
+        chg[v] = 1;
     };
     if (k <= NT) {
-      if (tg < G && tv != s) lds_min(&L.red[tv], relax_target(tv, tg));
+      if (tg < G && tv != s) relax_target(tv, tg);
     } else {
       for (int v = tid; v < k; v += NT)
-        if (v != s) L.red[v] = relax_target(v, 0);
+        if (v != s) relax_target(v, 0);
     }
     __syncthreads();
     int32_t *Fn = cur ? L.front0 : L.front1;
-    uint64_t *FBn = cur ? L.fbase0 : L.fbase1;
+    int32_t *FOn = reinterpret_cast<int32_t *>(cur ? L.fbase0 : L.fbase1);
     for (int vb = 0; vb < k; vb += NT) {
       const int v = vb + tid;
-      bool ch = false;
-      if (v < k) {
-        const uint64_t c = L.red[v];
-        if (c != KEY_NONE) {
-          L.red[v] = KEY_NONE;
-          const int64_t d = cand_dist(c);
-          if (d < L.dist[v]) {
-            L.dist[v] = d;
-            L.pred[v] = cand_node(c);
-            L.hop[v] = t;
-            ch = true;
-          }
-        }
-      }
+      const bool ch = v < k && chg[v];
+      if (ch) chg[v] = 0;
       // one LDS atomic per wavefront for the frontier append
       const uint64_t mask = __ballot(ch);
       if (mask) {
@@ -453,8 +463,8 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
         if ((tid & 63) == 0) base = atomicAdd(&S.nfront[cur ^ 1], __popcll(mask));
         base = __builtin_amdgcn_readlane(base, 0);
         if (ch) {
-          Fn[base + lanes_below(mask)] = v * k;
-          FBn[base + lanes_below(mask)] = pack_cand(L.dist[v], v);
+          Fn[base + lanes_below(mask)] = v;
+          FOn[base + lanes_below(mask)] = v * k;
         }
       }
     }
@@ -465,6 +475,14 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
     if (tid == 0) S.nfront[cur] = 0;
     if (nnext == 0) { conv = true; break; }
     cur ^= 1;
+  }
+  // unpack (chg is all zero again, and hop takes its place)
+  for (int v = tid; v < k; v += NT) {
+    const uint64_t l = lab[v];
+    const bool r = l != KEY_NONE;
+    L.dist[v] = r ? (int64_t)(l >> 22) - LAB_BIAS : DIST_NONE;
+    L.hop[v] = r ? (int32_t)((l >> 11) & 0x7ff) : -1;
+    L.pred[v] = (r && v != s) ? (int32_t)(l & 0x7ff) : -1;
   }
   if (tid == 0) {
     S.stats[ST_BF_ROUNDS] += rounds;
