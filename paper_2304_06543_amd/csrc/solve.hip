@@ -85,6 +85,7 @@ struct Scalars {
   int32_t ratio;    // cost of a Bellman-Ford round in Dijkstra steps, x16
   int32_t depth;    // running mean of (deepest hop + 1) of recent searches, x16
   int32_t maxhop;   // deepest hop of the last search in Dijkstra order
+  int32_t jflags[2];  // join_center's result, by iteration parity
 };
 
 }  // namespace
@@ -154,67 +155,98 @@ __device__ inline uint64_t list_threshold(const uint64_t (&a)[BEST_M], int c, bo
 // Unit x (row x) joins center v: its keys enter v's lists, row v of W follows.
 // Returns (block-wide) bit 0: some W entry decreased; bit 1: a decreased entry
 // breaks the node potentials.
-__device__ __forceinline__ int join_center(const InstView &I, const Lds &L, int x, int v) {
+// The key of unit x (row x) enters the list of (v, w); row v of W follows.
+// Sets changed when W[v][w] decreased, breaks when that breaks the node
+// potentials.
+__device__ __forceinline__ void join_one(const InstView &I, const Lds &L, int x, int v, int w,
+                                         int &changed, int &breaks) {
   const int k = I.k;
   const int32_t *rx = I.cm + (int64_t)x * k;
   const int32_t base = rx[v];
-  int changed = 0, breaks = 0;
-  for (int w = threadIdx.x; w < k; w += NT) {
-    if (w == v) continue;
-    const int32_t delta = rx[w] - base;
-    const uint64_t q = pack_key(delta, (uint32_t)x);
-    const int64_t idx = (int64_t)v * k + w;
-    // with every unit held q always enters; otherwise only in front of a held
-    // key (beyond the last held key an unheld unit may be smaller)
-    if (!(q < I.thr[idx])) continue;
-    const uint8_t meta = I.meta[idx];
-    const int c = meta & 15;
-    const bool all = meta & META_ALL;
-    uint64_t a[BEST_M];
-    list_load(I.best + idx * BEST_M, a);
-    list_merge(a, q);
-    list_store(I.best + idx * BEST_M, a);
-    const bool full = c == BEST_M;
-    const int c2 = full ? BEST_M : c + 1;
-    const bool all2 = all && !full;
-    I.meta[idx] = (uint8_t)(c2 | (all2 ? META_ALL : 0));
-    I.thr[idx] = list_threshold(a, c2, all2);
-    if (a[0] < L.W[idx]) {
-      set_w(L, idx, a[0]);
-      changed = 1;
-      breaks |= L.pot[v] + delta < L.pot[w];
-    }
+  const int32_t delta = rx[w] - base;
+  const uint64_t q = pack_key(delta, (uint32_t)x);
+  const int64_t idx = (int64_t)v * k + w;
+  // with every unit held q always enters; otherwise only in front of a held
+  // key (beyond the last held key an unheld unit may be smaller)
+  if (!(q < I.thr[idx])) return;
+  const uint8_t meta = I.meta[idx];
+  const int c = meta & 15;
+  const bool all = meta & META_ALL;
+  uint64_t a[BEST_M];
+  list_load(I.best + idx * BEST_M, a);
+  list_merge(a, q);
+  list_store(I.best + idx * BEST_M, a);
+  const bool full = c == BEST_M;
+  const int c2 = full ? BEST_M : c + 1;
+  const bool all2 = all && !full;
+  I.meta[idx] = (uint8_t)(c2 | (all2 ? META_ALL : 0));
+  I.thr[idx] = list_threshold(a, c2, all2);
+  if (a[0] < L.W[idx]) {
+    set_w(L, idx, a[0]);
+    changed = 1;
+    breaks |= L.pot[v] + delta < L.pot[w];
   }
-  const int c = __syncthreads_or(changed);
-  const int b = __syncthreads_or(breaks);
-  return c | (b << 1);
 }
 
-// Unit x leaves center u: its keys leave u's lists.  Lists that become
-// unknown are left for refill_center.
-__device__ __forceinline__ void leave_center(const InstView &I, const Lds &L, int x, int u) {
+// Unit x joins center v.  Returns (workgroup-wide) bit 0: some W entry
+// decreased; bit 1: a decreased entry breaks the node potentials.  The two
+// bits meet in one LDS word (one barrier); iterations alternate between two
+// words so the other one can be cleared without another barrier.
+__device__ __forceinline__ int join_center(const InstView &I, const Lds &L, Scalars &S, int x, int v,
+                                           int parity) {
+  const int k = I.k;
+  int changed = 0, breaks = 0;
+  for (int w = threadIdx.x; w < k; w += NT)
+    if (w != v) join_one(I, L, x, v, w, changed, breaks);
+  const uint64_t mc = __ballot(changed), mb = __ballot(breaks);
+  if ((threadIdx.x & 63) == 0 && (mc | mb)) atomicOr(&S.jflags[parity], (mc ? 1 : 0) | (mb ? 2 : 0));
+  __syncthreads();
+  const int f = S.jflags[parity];
+  if (threadIdx.x == 0) S.jflags[parity ^ 1] = 0;
+  return f;
+}
+
+// The key of unit x (row x) leaves the list of (u, w).  A list that becomes
+// unknown is left for refill_center.
+__device__ __forceinline__ void leave_one(const InstView &I, const Lds &L, int x, int u, int w) {
   const int k = I.k;
   const int32_t *rx = I.cm + (int64_t)x * k;
   const int32_t base = rx[u];
-  for (int w = threadIdx.x; w < k; w += NT) {
-    if (w == u) continue;
-    const uint64_t q = pack_key(rx[w] - base, (uint32_t)x);
-    const int64_t idx = (int64_t)u * k + w;
-    const uint8_t meta = I.meta[idx];
-    const int c = meta & 15;
-    uint64_t a[BEST_M];
-    list_load(I.best + idx * BEST_M, a);
-    bool held = false;
+  const uint64_t q = pack_key(rx[w] - base, (uint32_t)x);
+  const int64_t idx = (int64_t)u * k + w;
+  const uint8_t meta = I.meta[idx];
+  const int c = meta & 15;
+  uint64_t a[BEST_M];
+  list_load(I.best + idx * BEST_M, a);
+  bool held = false;
 #pragma unroll
-    for (int i = 0; i < BEST_M; ++i) held |= a[i] == q;
-    if (!held) continue;                         // not among the c smallest: lists unchanged
+  for (int i = 0; i < BEST_M; ++i) held |= a[i] == q;
+  if (!held) return;                           // not among the c smallest: lists unchanged
 #pragma unroll
-    for (int i = 0; i < BEST_M - 1; ++i) a[i] = a[i] < q ? a[i] : a[i + 1];
-    a[BEST_M - 1] = KEY_NONE;
-    list_store(I.best + idx * BEST_M, a);
-    I.meta[idx] = (uint8_t)((c - 1) | (meta & META_ALL));
-    I.thr[idx] = list_threshold(a, c - 1, meta & META_ALL);
-    set_w(L, idx, a[0]);                         // stale if unknown; refill sets it
+  for (int i = 0; i < BEST_M - 1; ++i) a[i] = a[i] < q ? a[i] : a[i + 1];
+  a[BEST_M - 1] = KEY_NONE;
+  list_store(I.best + idx * BEST_M, a);
+  I.meta[idx] = (uint8_t)((c - 1) | (meta & META_ALL));
+  I.thr[idx] = list_threshold(a, c - 1, meta & META_ALL);
+  set_w(L, idx, a[0]);                         // stale if unknown; refill sets it
+}
+
+// The moved units of an applied refinement leave their old centers' lists,
+// then join their new centers' lists.  The old centers of a refinement are
+// distinct, and so are the new ones, so each pass updates disjoint lists and
+// covers all moves at once (threads over (move, target) pairs).
+__device__ __forceinline__ void move_lists(const InstView &I, const Lds &L, int nmov) {
+  const int k = I.k;
+  const int total = nmov * k;
+  for (int t = threadIdx.x; t < total; t += NT) {
+    const int e = t / k, w = t - e * k;
+    if (w != L.mfrom[e]) leave_one(I, L, L.mrow[e], L.mfrom[e], w);
+  }
+  __syncthreads();
+  int changed = 0, breaks = 0;                   // the potentials are rechecked afterwards
+  for (int t = threadIdx.x; t < total; t += NT) {
+    const int e = t / k, w = t - e * k;
+    if (w != L.mto[e]) join_one(I, L, L.mrow[e], L.mto[e], w, changed, breaks);
   }
   __syncthreads();
 }
@@ -761,8 +793,7 @@ __device__ __forceinline__ bool refine(const InstView &I, const Lds &L, Scalars 
   const int64_t t0 = tid == 0 ? now() : 0;
   // every unit leaves its old center's lists before any joins the new ones;
   // lists left unknown are refilled from the final members
-  for (int e = 0; e < nmov; ++e) leave_center(I, L, L.mrow[e], L.mfrom[e]);
-  for (int e = 0; e < nmov; ++e) join_center(I, L, L.mrow[e], L.mto[e]);
+  move_lists(I, L, nmov);
   for (int e = 0; e < nmov; ++e) refill_center(I, L, S, L.mfrom[e]);
   if (tid == 0) S.stats[ST_T_RESCAN] += now() - t0;
   __syncthreads();
@@ -820,6 +851,7 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
     // (an empty table is certified by the zero potential)
     S.pot_ok = r_begin == 0;
     S.depth = 0;
+    S.jflags[0] = S.jflags[1] = 0;
     S.ratio = (int32_t)min(max(I.scalars[SC_RATIO], (int64_t)0), MAX_SEARCH_RATIO);
     S.obj = I.scalars[SC_OBJECTIVE];
     S.status = (int32_t)I.scalars[SC_STATUS];
@@ -844,7 +876,7 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
         L.load[s] = ld + 1;
         S.obj += (int64_t)row[s] + (vac ? 0 : L.pen[s]);
       }
-      const int ins = join_center(I, L, (int)r, s);   // contains barriers
+      const int ins = join_center(I, L, S, (int)r, s, (int)(r & 1));   // contains a barrier
       const int64_t t1 = tid == 0 ? now() : 0;
       // Negative Cycle Refinement can only find something if the current W
       // may hold a negative cycle: the insert lowered an entry and the node
