@@ -122,7 +122,8 @@ int lbdd_snapshot(lbdd_instance *h, int32_t *load, uint64_t *W, int64_t *order);
  *   [7] iterations done  [8] cycle searches skipped because the node
  *       potentials prove the table has no negative cycle
  *   [9] .. [12] device timer ticks spent in: allotment, cycle refinement,
- *       path refinement, list updates and refills after applied refinements
+ *       path refinement (these three sampled on one iteration in 8 and
+ *       scaled by 8), list updates and refills after applied refinements
  *       (part of [10], [11])
  *   [13] best-transfer list refills (column scans of one center's members)
  *   [14] device timer when the instance's first solve launch began, [15] when

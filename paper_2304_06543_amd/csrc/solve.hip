@@ -331,6 +331,38 @@ __device__ __forceinline__ void refill_center(const InstView &I, const Lds &L, S
   for (int j = 0; j < nr; ++j) refill_column(I, L, S, u, L.trow[j]);
 }
 
+// Refill every unknown list of the old centers of an applied refinement's
+// moves: one pass finds them all (most moves leave none), then each is
+// refilled.  Refills read only the final member lists, so their order does
+// not matter.  More unknown lists than slots (k + 1) falls back to one center
+// at a time.
+__device__ __forceinline__ void refill_moved(const InstView &I, const Lds &L, Scalars &S, int nmov) {
+  const int k = I.k;
+  if (threadIdx.x == 0) S.nrefill = 0;
+  __syncthreads();
+  const int total = nmov * k;
+  for (int t = threadIdx.x; t < total; t += NT) {
+    const int e = t / k, w = t - e * k;
+    const int u = L.mfrom[e];
+    if (w == u) continue;
+    const uint8_t meta = I.meta[(int64_t)u * k + w];
+    if ((meta & 15) == 0 && !(meta & META_ALL)) {
+      const int j = atomicAdd(&S.nrefill, 1);
+      if (j <= k) L.trow[j] = e << 16 | w;
+    }
+  }
+  __syncthreads();
+  const int nr = S.nrefill;
+  if (nr <= k + 1) {
+    for (int j = 0; j < nr; ++j) {
+      const int p = L.trow[j];
+      refill_column(I, L, S, L.mfrom[p >> 16], p & 0xffff);
+    }
+  } else {
+    for (int e = 0; e < nmov; ++e) refill_center(I, L, S, L.mfrom[e]);
+  }
+}
+
 // After a search that applied nothing the labels are a feasible potential:
 // dist[v] <= dist[u] + W[u][v] holds for edges between centers by the
 // Bellman-Ford fixpoint (every center is reachable: the anchor holds at
@@ -794,7 +826,7 @@ __device__ __forceinline__ bool refine(const InstView &I, const Lds &L, Scalars 
   // every unit leaves its old center's lists before any joins the new ones;
   // lists left unknown are refilled from the final members
   move_lists(I, L, nmov);
-  for (int e = 0; e < nmov; ++e) refill_center(I, L, S, L.mfrom[e]);
+  refill_moved(I, L, S, nmov);
   if (tid == 0) S.stats[ST_T_RESCAN] += now() - t0;
   __syncthreads();
   if (S.status == 0) retry_potential(I, L, S, s, nmov);
@@ -863,7 +895,10 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
   int64_t r = r_begin;
   if (ok0) {
     for (; r < r_end; ++r) {
-      const int64_t t0 = tid == 0 ? now() : 0;   // phase timers: thread 0 only
+      // phase timers: thread 0, one iteration in 8 (a timer read holds up
+      // the next barrier), scaled by 8
+      const bool timed = tid == 0 && (r & 7) == 0;
+      const int64_t t0 = timed ? now() : 0;
       const int s = I.smin[r];
       const int32_t *row = I.cm + r * k;
       if (tid == 0) {
@@ -877,7 +912,7 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
         S.obj += (int64_t)row[s] + (vac ? 0 : L.pen[s]);
       }
       const int ins = join_center(I, L, S, (int)r, s, (int)(r & 1));   // contains a barrier
-      const int64_t t1 = tid == 0 ? now() : 0;
+      const int64_t t1 = timed ? now() : 0;
       // Negative Cycle Refinement can only find something if the current W
       // may hold a negative cycle: the insert lowered an entry and the node
       // potentials no longer certify that W has none.
@@ -886,15 +921,15 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
       if (search) labels = refine<WLDS>(I, L, S, s, 0, false);
       else if (tid == 0) S.stats[ST_CYC_SKIPPED] += 1;
       __syncthreads();
-      const int64_t t2 = tid == 0 ? now() : 0;
+      const int64_t t2 = timed ? now() : 0;
       if (S.status != 0) break;
       if (!S.vacant) refine<WLDS>(I, L, S, s, 1, labels && S.status == 0);
       __syncthreads();
-      if (tid == 0) {
+      if (timed) {
         const int64_t t3 = now();
-        S.stats[ST_T_ALLOT] += t1 - t0;
-        S.stats[ST_T_CYCLE] += t2 - t1;
-        S.stats[ST_T_PATH] += t3 - t2;
+        S.stats[ST_T_ALLOT] += 8 * (t1 - t0);
+        S.stats[ST_T_CYCLE] += 8 * (t2 - t1);
+        S.stats[ST_T_PATH] += 8 * (t3 - t2);
       }
       if (S.status != 0) break;
     }
