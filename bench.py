@@ -167,7 +167,7 @@ def main():
     ap.add_argument("--scan-reps", type=int, default=10)
     ap.add_argument("--batch", type=int, default=16,
                     help="instances of the batched workload to compare batched vs plain (0: skip)")
-    ap.add_argument("--serve", type=int, default=0,
+    ap.add_argument("--serve", type=int, default=100,
                     help="requests of a Poisson trace to serve vs plain FIFO (0: skip)")
     ap.add_argument("--serve-max-n", type=int, default=200_000)
     ap.add_argument("--serve-max-k", type=int, default=256)
