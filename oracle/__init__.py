@@ -53,8 +53,9 @@ def _load(path: str = LIB):
     lib.orc_objective.argtypes = [C.c_int32, C.c_int64, P, P, P, P, P]
     lib.orc_refine_search.argtypes = [C.c_int32, P, C.c_int32, C.c_int32, P, P, P, P, P, P]
     lib.orc_solve.argtypes = [C.c_int32, C.c_int64, P, P, P, C.c_int64, P, P, P, P, P, P]
+    lib.orc_solve_strict.argtypes = [C.c_int32, C.c_int64, P, P, C.c_int64, P, P, P, P, P, P]
     for f in (lib.orc_setup, lib.orc_best_transfers, lib.orc_objective,
-              lib.orc_refine_search, lib.orc_solve):
+              lib.orc_refine_search, lib.orc_solve, lib.orc_solve_strict):
         f.restype = C.c_int
     if path == LIB:
         _lib = lib
@@ -157,6 +158,38 @@ def solve(cm, cap, pen, max_iters: int = -1, want_W: bool = False, want_trace: b
     if rc:
         raise OracleError(rc, "orc_solve")
     return Result(assign, load, int(obj[0]), W, trace[:iters] if trace is not None else None, stats)
+
+
+@dataclass
+class StrictResult:
+    assign: np.ndarray        # [n] center per unit id, -1 if left at the dummy center
+    load: np.ndarray          # [kx] units per center (dummy center last when added)
+    kx: int                   # k, or k + 1 with the dummy center of excess demand
+    objective: int            # Equation (3): sum of CM over allotted units
+    W: np.ndarray | None      # [kx][kx] best-transfer keys with dummy transfers
+    stats: np.ndarray
+
+
+DUMMY_KEY = np.uint64((1 << 63) | 0xFFFFFFFE)
+
+
+def solve_strict(cm, cap, max_iters: int = -1, want_W: bool = False, lib=None) -> StrictResult:
+    """Strict-LBDD, Algorithm 4 (Appendix B), run for min(n, max_iters) iterations."""
+    lib = lib or _load()
+    cm = _i32(cm)
+    n, k = cm.shape
+    iters = n if (max_iters < 0 or max_iters > n) else max_iters
+    assign = np.empty(n, np.int32); load = np.zeros(k + 1, np.int32)
+    kx = np.zeros(1, np.int32); obj = np.zeros(1, np.int64)
+    W = np.empty((k + 1) * (k + 1), np.uint64) if want_W else None
+    stats = np.zeros(STATS_N, np.int64)
+    rc = lib.orc_solve_strict(k, n, _p(cm), _p(_i32(cap)), iters, _p(assign), _p(load), _p(kx),
+                              _p(obj), _p(W) if W is not None else None, _p(stats))
+    if rc:
+        raise OracleError(rc, "orc_solve_strict")
+    m = int(kx[0])
+    return StrictResult(assign, load[:m], m, int(obj[0]),
+                        W[:m * m].reshape(m, m) if W is not None else None, stats)
 
 
 # -- key packing (the interface format of best-transfer keys) --------------

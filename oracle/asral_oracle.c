@@ -314,6 +314,7 @@ typedef struct {
     uint8_t *has;
     int32_t *pred;
     int64_t stats[ORC_STATS_N];
+    int strict;             /* strict-LBDD: dummy units fill every free slot */
 } orc_state;
 
 /* top of BestTransHeap(u,v), discarding entries whose unit has left u */
@@ -341,10 +342,18 @@ static int heaps_insert_unit(orc_state *S, int64_t d, int32_t u) {
     return ORC_OK;
 }
 
+/* Key of moving one of the zero-cost dummy units of strict-LBDD (Appendix B)
+ * out of a center with free capacity: transfer cost 0, ordered after every
+ * real unit's key of equal cost (the rank field is beyond any real rank).  */
+#define DUMMY_KEY (((uint64_t)1u << 63) | 0xFFFFFFFEu)
+
 static void refresh_W(orc_state *S) {
     for (int32_t u = 0; u < S->k; ++u)
-        for (int32_t v = 0; v < S->k; ++v)
-            S->W[(int64_t)u * S->k + v] = (u == v) ? KEY_NONE : heap_top(S, u, v);
+        for (int32_t v = 0; v < S->k; ++v) {
+            uint64_t key = (u == v) ? KEY_NONE : heap_top(S, u, v);
+            if (S->strict && u != v && S->load[u] < S->cap[u] && DUMMY_KEY < key) key = DUMMY_KEY;
+            S->W[(int64_t)u * S->k + v] = key;
+        }
 }
 
 /* One refinement (Algorithm 1 for mode 0, Appendix A for mode 1) with anchor s.
@@ -381,10 +390,11 @@ static int refine(orc_state *S, int32_t s, int mode, int64_t *applied, int64_t *
         int32_t v = path[len - 2 - e];
         if (v == k) v = s;                      /* s*_in is the anchor itself */
         uint64_t key = S->W[(int64_t)u * k + v];
-        units[e] = S->order[key_rank(key)];
+        units[e] = key == DUMMY_KEY ? -1 : S->order[key_rank(key)];   /* -1: a dummy unit */
         from[e] = u; to[e] = v;
     }
     for (int32_t e = 0; e < ntransfer; ++e) {
+        if (units[e] < 0) continue;             /* a dummy moves: no real unit does */
         S->a[units[e]] = to[e];
         S->load[from[e]] -= 1;
         S->load[to[e]] += 1;
@@ -392,7 +402,7 @@ static int refine(orc_state *S, int32_t s, int mode, int64_t *applied, int64_t *
     }
     int rc2 = ORC_OK;
     for (int32_t e = 0; e < ntransfer && !rc2; ++e)
-        rc2 = heaps_insert_unit(S, units[e], to[e]);
+        if (units[e] >= 0) rc2 = heaps_insert_unit(S, units[e], to[e]);
     *applied = S->dist[k];
     *edges = nedges;
     free(path); free(units); free(from); free(to);
@@ -483,5 +493,114 @@ int orc_solve(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap,
         if (stats) memcpy(stats, S.stats, sizeof(S.stats));
     }
     state_free(&S);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Strict-LBDD (Appendix B): no center may hold more units than its
+ * capacity, and the objective is Equation (3), the plain allotment cost.
+ *   Pre-processing: if the total capacity is below n, a dummy center with
+ *   index k, capacity n - sum(cap) and cost max(CM) + 1 for every unit is
+ *   added (it changes every complete allotment's cost by the same amount).
+ *   Every center's free capacity is held by zero-cost dummy units, so Gamma
+ *   has a zero-cost transfer u -> v for every v while u has free capacity.
+ *   Algorithm 4: each unit, in the MinDistance order of ASRAL, goes to the
+ *   cheapest center that still has free capacity (smallest index among equal
+ *   costs) and Negative Cycle Refinement (Algorithm 1) runs anchored there.
+ * Theorem 2: the result is an optimal allotment.
+ * Readings: the processing order is ASRAL's; a dummy transfer's key follows
+ * every real key of equal cost; applying a dummy transfer moves no real unit.
+ * Outputs: assign[n] (-1 for units left at the dummy center), load_out[kx]
+ * (kx = k or k + 1 with the dummy center, which *kx_out reports), objective
+ * = sum of CM over the allotted units, W_out[kx][kx] (dummy edges included),
+ * stats as orc_solve.                                                         */
+int orc_solve_strict(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap,
+                     int64_t max_iters, int32_t *assign, int32_t *load_out, int32_t *kx_out,
+                     int64_t *objective, uint64_t *W_out, int64_t *stats) {
+    if (k < 1 || n < 1 || !cm || !cap || !assign || !objective || !kx_out) return ORC_E_INVAL;
+    int64_t total = 0;
+    int32_t maxcm = 0;
+    for (int32_t s = 0; s < k; ++s) {
+        if (cap[s] < 0) return ORC_E_INVAL;
+        total += cap[s];
+    }
+    for (int64_t i = 0; i < n * (int64_t)k; ++i) {
+        if (cm[i] < 0 || cm[i] >= CM_LIMIT) return ORC_E_INVAL;
+        if (cm[i] > maxcm) maxcm = cm[i];
+    }
+    const int32_t kx = total < n ? k + 1 : k;
+    int32_t *cmx = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * kx);
+    int32_t *capx = (int32_t *)malloc(sizeof(int32_t) * (size_t)kx);
+    int32_t *pen1 = (int32_t *)malloc(sizeof(int32_t) * (size_t)kx);
+    if (!cmx || !capx || !pen1) { free(cmx); free(capx); free(pen1); return ORC_E_NOMEM; }
+    for (int64_t d = 0; d < n; ++d) {
+        memcpy(cmx + d * kx, cm + d * (int64_t)k, sizeof(int32_t) * (size_t)k);
+        if (kx > k) cmx[d * kx + k] = maxcm + 1;
+    }
+    for (int32_t s = 0; s < k; ++s) capx[s] = cap[s];
+    if (kx > k) capx[k] = (int32_t)(n - total);
+    for (int32_t s = 0; s < kx; ++s) pen1[s] = 1;        /* no penalties in strict-LBDD */
+
+    orc_state S;
+    memset(&S, 0, sizeof(S));
+    S.k = kx; S.n = n; S.cm = cmx; S.cap = capx; S.pen = pen1; S.strict = 1;
+    const int32_t K1 = kx + 1;
+    S.smin = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    S.mc = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    S.a = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    S.load = (int32_t *)calloc((size_t)kx, sizeof(int32_t));
+    S.order = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    S.rank = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    S.H = (heap_t *)calloc((size_t)kx * kx, sizeof(heap_t));
+    S.W = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)kx * kx);
+    S.wt = (int64_t *)malloc(sizeof(int64_t) * (size_t)K1 * K1);
+    S.has = (uint8_t *)malloc((size_t)K1 * K1);
+    S.dist = (int64_t *)malloc(sizeof(int64_t) * (size_t)K1);
+    S.scratch = (int64_t *)malloc(sizeof(int64_t) * (size_t)K1);
+    S.pred = (int32_t *)malloc(sizeof(int32_t) * (size_t)K1);
+    int rc = ORC_OK;
+    if (!S.smin || !S.mc || !S.a || !S.load || !S.order || !S.rank || !S.H || !S.W ||
+        !S.wt || !S.has || !S.dist || !S.scratch || !S.pred)
+        rc = ORC_E_NOMEM;
+    if (!rc) rc = orc_setup(kx, n, cmx, S.smin, S.mc, S.order, S.rank);
+    int64_t delta = 0;
+    if (!rc) {
+        for (int64_t d = 0; d < n; ++d) S.a[d] = -1;
+        int64_t iters = (max_iters < 0 || max_iters > n) ? n : max_iters;
+        for (int64_t r = 0; r < iters && !rc; ++r) {
+            int64_t d = S.order[r];
+            const int32_t *row = cmx + d * kx;
+            int32_t s = -1;                          /* cheapest center with free capacity */
+            for (int32_t t = 0; t < kx; ++t)
+                if (S.load[t] < capx[t] && (s < 0 || row[t] < row[s])) s = t;
+            S.a[d] = s;
+            S.load[s] += 1;
+            delta += row[s];
+            rc = heaps_insert_unit(&S, d, s);
+            if (rc) break;
+            int64_t gain = 0, len = 0;
+            int32_t rounds = 0;
+            S.stats[3]++;
+            rc = refine(&S, s, 0, &gain, &len, &rounds);
+            if (rc) break;
+            if (gain < 0) { delta += gain; S.stats[0]++; }
+            S.stats[7] = r + 1;
+        }
+    }
+    if (!rc) {
+        int64_t at_dummy = 0;
+        for (int64_t d = 0; d < n; ++d) {
+            int32_t c = S.a[d];
+            if (kx > k && c == k) { ++at_dummy; c = -1; }
+            assign[d] = c;
+        }
+        *objective = delta - at_dummy * ((int64_t)maxcm + 1);
+        *kx_out = kx;
+        if (load_out) memcpy(load_out, S.load, sizeof(int32_t) * (size_t)kx);
+        if (W_out) { refresh_W(&S); memcpy(W_out, S.W, sizeof(uint64_t) * (size_t)kx * kx); }
+        if (stats) memcpy(stats, S.stats, sizeof(S.stats));
+    }
+    state_free(&S);
+    free(cmx); free(capx); free(pen1);
     return rc;
 }

@@ -108,3 +108,41 @@ def min_simple_path(E, k, src):
             if ok and (best is None or cost < best):
                 best = cost
     return best
+
+
+def opt_strict(cm, cap) -> int:
+    """Exact optimum of strict-LBDD (Appendix B, Equation (3)): center s gets
+    cap[s] slots at cost CM(d,s); with excess demand n - sum(cap) more slots
+    at a cost above every CM entry take the units no center can hold (their
+    cost, the same for every complete allotment, is subtracted); scipy's
+    assignment solver matches units to slots."""
+    cm = np.asarray(cm, np.int64)
+    n, k = cm.shape
+    total = int(np.sum(cap))
+    big = int(cm.max()) + 1
+    cols = [np.repeat(cm[:, s:s + 1], int(cap[s]), axis=1) for s in range(k) if cap[s] > 0]
+    excess = max(0, n - total)
+    if excess:
+        cols.append(np.full((n, excess), big, np.int64))
+    cost = np.concatenate(cols, axis=1)
+    r, c = linear_sum_assignment(cost)
+    return int(cost[r, c].sum()) - excess * big
+
+
+def strict_brute(cm, cap) -> int:
+    """Strict-LBDD optimum by enumerating every allotment that respects the
+    capacities (units beyond the total capacity may stay unallotted, exactly
+    max(0, n - sum(cap)) of them, at no cost)."""
+    cm = np.asarray(cm, np.int64)
+    n, k = cm.shape
+    excess = max(0, n - int(np.sum(cap)))
+    best = None
+    for a in itertools.product(range(-1, k), repeat=n):
+        a = np.array(a)
+        if int((a < 0).sum()) != excess:
+            continue
+        if any(int((a == s).sum()) > cap[s] for s in range(k)):
+            continue
+        v = int(sum(cm[d, a[d]] for d in range(n) if a[d] >= 0))
+        best = v if best is None or v < best else best
+    return best

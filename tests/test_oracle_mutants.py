@@ -32,6 +32,9 @@ MUTANTS = {
                               "uint64_t key = W[(int64_t)v * k + u];\n            if (key == KEY_NONE) continue;\n            wt"),
     "cycle_in_edge_reversed": ("uint64_t key = W[(int64_t)u * k + anchor];", "uint64_t key = W[(int64_t)anchor * k + u];"),
     "bf_stops_early": ("for (int32_t t = 1; t <= K1; ++t) {", "for (int32_t t = 1; t <= 2; ++t) {"),
+    "strict_no_dummy_edges": ("if (S->strict && u != v", "if (0 && u != v"),
+    "strict_allot_ignores_capacity": ("if (S.load[t] < capx[t] && (s < 0", "if ((s < 0"),
+    "strict_dummy_cost_not_above_max": ("cmx[d * kx + k] = maxcm + 1;", "cmx[d * kx + k] = maxcm;"),
 }
 
 
@@ -94,8 +97,22 @@ def _pin_failures(lib):
                 return False
         return True
 
+    def strict_ok():
+        for s in range(10):
+            rng = np.random.default_rng(900 + s)
+            k, n = 2 + s % 4, 30
+            cm = rng.integers(0, 30, size=(n, k)).astype(np.int32)
+            cap = rng.integers(0, 2 * n // k, size=k).astype(np.int32)
+            r = oracle.solve_strict(cm, cap, lib=lib)
+            real = r.assign >= 0
+            if (np.bincount(r.assign[real], minlength=k) > cap).any():
+                return False
+            if r.objective != pins.opt_strict(cm, cap):
+                return False
+        return True
+
     for name, fn in [("setup", setup_ok), ("hand_trace", hand_trace_ok), ("search", search_ok),
-                     ("solve", solve_ok), ("zero_cap", zero_cap_ok)]:
+                     ("solve", solve_ok), ("zero_cap", zero_cap_ok), ("strict", strict_ok)]:
         check(name, fn)
     return fails
 
