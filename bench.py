@@ -106,7 +106,38 @@ def run_batch(m, lbdd, L, torch, dev):
             "plain_solves_per_s": round(m / seq_s, 3), "speedup": round(seq_s / bat_s, 2),
             "latency_from_launch_p50_s": round(float(np.percentile(lat, 50)), 3),
             "latency_from_launch_p99_s": round(float(np.percentile(lat, 99)), 3),
-            "identical_to_plain": objs == plain_obj}
+            "identical_to_plain": objs == plain_obj, "_objectives": objs}
+
+
+def _oracle_solve(args):
+    """Worker of the instance-parallel CPU baseline: one whole oracle solve."""
+    import oracle
+    cm, cap, pen = args
+    t = time.perf_counter()
+    r = oracle.solve(cm, cap, pen)
+    return r.objective, time.perf_counter() - t
+
+
+def run_cpu_batch(m, L, gpu_objs):
+    """The same m batched instances solved by the CPU oracle, one instance per
+    host process on all host cores (at most 16, one GPU's share of a box)."""
+    import multiprocessing as mp
+    specs = L.batch_specs()[:m]
+    insts = [L.make_batch_instance(sp) for sp in specs]
+    cores = min(16, os.cpu_count() or 1, m)
+    log(f"bench: CPU oracle on the {m} batched instances, {cores} processes")
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = []
+        for j, r in enumerate(pool.imap(_oracle_solve, [i.arrays() for i in insts])):
+            res.append(r)
+            log(f"bench: oracle batch: {j + 1}/{m} done, {time.perf_counter() - t0:.1f} s")
+    wall = time.perf_counter() - t0
+    objs = [o for o, _ in res]
+    return {"value": round(m / wall, 4), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"the same {m} instances, whole solves, one per process ({wall:.1f} s wall, "
+                      f"{sum(t for _, t in res):.1f} s of CPU)",
+            "objectives_match_gpu": objs == gpu_objs}
 
 
 def run_serve(count, max_n, max_k, lbdd, L):
@@ -171,6 +202,10 @@ def main():
                     help="requests of a Poisson trace to serve vs plain FIFO (0: skip)")
     ap.add_argument("--serve-max-n", type=int, default=200_000)
     ap.add_argument("--serve-max-k", type=int, default=256)
+    ap.add_argument("--no-strict", action="store_true",
+                    help="skip the strict-LBDD (Appendix B) solve of the same instance")
+    ap.add_argument("--cpu-batch", action="store_true",
+                    help="also time the CPU oracle on the batched instances, one per host process")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (search choice on a solve prefix, scan tiles)")
     ap.add_argument("--tune-iters", type=int, default=0,
@@ -198,7 +233,8 @@ def main():
     cm = torch.from_numpy(inst.cm).to(dev)
     torch.cuda.synchronize()
     with open(os.path.join(ROOT, "tests", "golden", "oracle_results.json")) as f:
-        gold = json.load(f)["C2"]
+        golds = json.load(f)
+    gold, gold_strict = golds["C2"], golds["C2_strict"]
 
     tune = {}
     if not args.no_tune:
@@ -314,8 +350,40 @@ def main():
         del src, dst
 
     batch = run_batch(args.batch, lbdd, L, torch, dev) if args.batch > 0 else None
+    if batch is not None:
+        objs_b = batch.pop("_objectives")
+        if args.cpu_batch:
+            batch["cpu_baseline"] = run_cpu_batch(args.batch, L, objs_b)
     serve = (run_serve(args.serve, args.serve_max_n, args.serve_max_k, lbdd, L)
              if args.serve > 0 else None)
+
+    strict = None
+    if not args.no_strict:
+        def strict_step():
+            h = lbdd.Instance(cm, inst.cap, stream=stream, strict=True)
+            ev0.record(stream)
+            h.solve()
+            ev1.record(stream)
+            o, st = h.objective(), h.stats()
+            h.close()
+            return o, st, ev0.elapsed_time(ev1)
+
+        log("bench: strict-LBDD solve of the same instance (warmup + timed)")
+        strict_step()
+        sms, sobjs, sst = [], [], None
+        for _ in range(args.steps):
+            o, sst, ms = strict_step()
+            sobjs.append(o)
+            sms.append(ms)
+        smean = float(np.mean(sms))
+        strict = {"workload": "strict-LBDD (Appendix B, Algorithm 4) on the same k=100 n=100000 "
+                              "instance: capacities total 0.95n, so a dummy center takes the "
+                              "5,000 units beyond them",
+                  "solve_ms": round(smean, 3), "solves_per_s": round(1e3 / smean, 4),
+                  "objective": sobjs[-1],
+                  "objective_matches_oracle": all(o == gold_strict["objective"] for o in sobjs),
+                  "stats": sst}
+        log(f"bench: strict solve {smean:.1f} ms, parity {strict['objective_matches_oracle']}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -328,6 +396,15 @@ def main():
                "sample": f"one whole solve of the k=100 n=100000 instance ({dt:.1f} s); "
                          f"objective {'matches' if r.objective == gold['objective'] else 'DIFFERS'}"}
         log(f"bench: oracle {dt:.1f} s")
+        if strict is not None:
+            tc = time.perf_counter()
+            rs = oracle.solve_strict(inst.cm, inst.cap)
+            dts = time.perf_counter() - tc
+            strict["cpu_baseline"] = {
+                "value": round(1.0 / dts, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+                "sample": f"one whole strict solve of the same instance ({dts:.1f} s); objective "
+                          f"{'matches' if rs.objective == gold_strict['objective'] else 'DIFFERS'}"}
+            log(f"bench: strict oracle {dts:.1f} s")
 
     out = {
         "metric": "cost-matrix GB/s (% HBM peak); LBDD solves/sec and p99 latency, batched vs plain",
@@ -348,6 +425,7 @@ def main():
         "tune": tune or None,
         "batch": batch,
         "serve": serve,
+        "strict": strict,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -85,6 +85,33 @@ int lbdd_create(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity
                 const int32_t *penalty, uint32_t flags, void *hip_stream,
                 lbdd_instance **out);
 
+/* Create a strict-LBDD instance (Appendix B): no center may take more units
+ * than its capacity and the objective is Equation (3), the sum of CM over the
+ * allotment.  Solved by Algorithm 4, which Theorem 2 makes exact: each unit
+ * (in the MinDistance order of lbdd_create) goes to the cheapest center that
+ * still has free capacity (smallest index among equal costs), then Negative
+ * Cycle Refinement runs anchored there.  Free capacity is held by zero-cost
+ * dummy units, so a center with free capacity has a zero-cost transfer to
+ * every other center; such a transfer orders after every real transfer of
+ * cost 0 and applying it moves no unit.
+ *   k, n, cm, flags, hip_stream, out   as lbdd_create
+ *   capacity    [k] int32 >= 0 host array, copied
+ * With excess demand (n > sum of capacities) the instance gets a dummy center
+ * k of capacity n - sum whose cost is (largest CM entry + 1) for every unit:
+ * lbdd_centers then reports k + 1, lbdd_snapshot's load and W cover it, the
+ * units left there are -1 in lbdd_assignment, and lbdd_objective leaves
+ * their constant cost out.  Then k must be below LBDD_MAX_K and every CM
+ * entry below 2^30 - 1.  lbdd_solve, lbdd_solve_iters, lbdd_solve_batch,
+ * lbdd_objective, lbdd_assignment, lbdd_progress, lbdd_snapshot, lbdd_stats
+ * and lbdd_destroy work as for any instance (the path counters stay 0).
+ * Errors: as lbdd_create. */
+int lbdd_create_strict(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity,
+                       uint32_t flags, void *hip_stream, lbdd_instance **out);
+
+/* Number of centers of the instance's graph Gamma: k, or k + 1 for a strict
+ * instance with a dummy center.  Errors: LBDD_E_INVAL (NULL). */
+int lbdd_centers(lbdd_instance *h, int32_t *k_graph);
+
 /* Run all remaining iterations of Algorithm 2 (allot, Algorithm 1, and
  * Appendix A when the receiving center was full).  Asynchronous: enqueued on
  * the instance's stream.  Calling it on a solved instance does nothing.
@@ -108,11 +135,12 @@ int lbdd_assignment(lbdd_instance *h, int32_t *out, uint32_t flags);
 /* Number of iterations done so far (0..n).  Synchronises. */
 int lbdd_progress(lbdd_instance *h, int64_t *iters_done);
 
-/* State snapshot for inspection, all host memory: load [k] int32 (units per
- * center), W [k][k] uint64 best-transfer keys of the allotment-subspace graph
- * (Definition of Gamma, Section 3.2; key = ((delta + 2^31) << 32) | rank,
- * all ones = no transfer), order [n] int64 (unit index at each processing
- * position).  Any pointer may be NULL.  Synchronises. */
+/* State snapshot for inspection, all host memory, with k = lbdd_centers:
+ * load [k] int32 (units per center), W [k][k] uint64 best-transfer keys of
+ * the allotment-subspace graph (Definition of Gamma, Section 3.2; key =
+ * ((delta + 2^31) << 32) | rank, all ones = no transfer; a strict instance's
+ * dummy transfer is (2^31 << 32) | (2^32 - 2)), order [n] int64 (unit index
+ * at each processing position).  Any pointer may be NULL.  Synchronises. */
 int lbdd_snapshot(lbdd_instance *h, int32_t *load, uint64_t *W, int64_t *order);
 
 /* Counters (int64, up to `count` of them, host memory):

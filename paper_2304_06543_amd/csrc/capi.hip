@@ -99,23 +99,45 @@ extern "C" {
 
 const char *lbdd_last_error(void) { return g_err.c_str(); }
 
-int lbdd_create(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity,
-                const int32_t *penalty, uint32_t flags, void *hip_stream, lbdd_instance **out) {
+}  // extern "C"
+
+namespace {
+
+// lbdd_create and lbdd_create_strict.  A strict instance with excess demand
+// gets the dummy center as its center k (capacity n - sum, cost largest
+// entry + 1); its penalties are unused.
+int create_instance(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity,
+                    const int32_t *penalty, uint32_t flags, void *hip_stream, bool strict,
+                    lbdd_instance **out) {
   g_err.clear();
   if (!out) return fail(LBDD_E_INVAL, "out is NULL");
   *out = nullptr;
   if (k < 1 || k > LBDD_MAX_K) return fail(LBDD_E_INVAL, "k=%d outside [1, %d]", k, LBDD_MAX_K);
   if (n < 1 || n > LBDD_MAX_N) return fail(LBDD_E_INVAL, "n=%lld outside [1, 2^31-1]", (long long)n);
-  if (!cm || !capacity || !penalty) return fail(LBDD_E_INVAL, "NULL input array");
+  if (!cm || !capacity || (!penalty && !strict)) return fail(LBDD_E_INVAL, "NULL input array");
   if (flags & ~LBDD_CM_DEVICE) return fail(LBDD_E_INVAL, "unknown flags 0x%x", flags);
+  int64_t total = 0;
   for (int32_t s = 0; s < k; ++s) {
     if (capacity[s] < 0) return fail(LBDD_E_INVAL, "capacity[%d]=%d < 0", s, capacity[s]);
-    if (penalty[s] < 1 || penalty[s] >= lbdd::CM_LIMIT)
+    total += capacity[s];
+    if (!strict && (penalty[s] < 1 || penalty[s] >= lbdd::CM_LIMIT))
       return fail(LBDD_E_INVAL, "penalty[%d]=%d outside [1, 2^30)", s, penalty[s]);
   }
+  const bool dummy = strict && total < n;
+  if (dummy && k == LBDD_MAX_K)
+    return fail(LBDD_E_INVAL, "excess demand needs a dummy center: k=%d must be below %d", k, LBDD_MAX_K);
+  const int32_t k_user = k;
+  std::vector<int32_t> capx(capacity, capacity + k), penx;
+  if (strict) {
+    if (dummy) { capx.push_back((int32_t)(n - total)); k += 1; }
+    penx.assign((size_t)k, 1);                    // strict-LBDD has no penalties
+    penalty = penx.data();
+  }
+  capacity = capx.data();
   lbdd_instance *h = new (std::nothrow) lbdd_instance;
   if (!h) return fail(LBDD_E_NOMEM, "host allocation");
   h->k = k; h->n = n; h->st = static_cast<hipStream_t>(hip_stream);
+  h->strict = strict; h->k_user = k_user; h->dummy = dummy ? k_user : -1;
   const size_t nk = (size_t)n * (size_t)k;
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = dalloc(&h->cm, nk, h->st);
@@ -138,17 +160,31 @@ int lbdd_create(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity
 
   // setup scratch: the unpermuted CM (host input only), sort keys, a flag
   const int32_t *cm_dev = cm;
-  int32_t *cm_tmp = nullptr, *bad = nullptr;
+  int32_t *cm_tmp = nullptr, *cm_ext = nullptr, *bad = nullptr, *mx = nullptr;
+  int32_t mx_h = 0;                  // read by an async copy: lives until the sync below
   void *work = nullptr;
   int64_t ratio = 0;                 // read by an async copy: lives until the sync below
   int rc = LBDD_OK;
   do {
     if (!(flags & LBDD_CM_DEVICE)) {
-      if ((e = dalloc(&cm_tmp, nk, h->st)) != hipSuccess) { rc = hip_fail(e, "device allocation"); break; }
-      if ((e = hipMemcpyAsync(cm_tmp, cm, nk * 4, hipMemcpyHostToDevice, h->st)) != hipSuccess) {
+      const size_t nk_user = (size_t)n * (size_t)k_user;
+      if ((e = dalloc(&cm_tmp, nk_user, h->st)) != hipSuccess) { rc = hip_fail(e, "device allocation"); break; }
+      if ((e = hipMemcpyAsync(cm_tmp, cm, nk_user * 4, hipMemcpyHostToDevice, h->st)) != hipSuccess) {
         rc = hip_fail(e, "copy CM to device"); break;
       }
       cm_dev = cm_tmp;
+    }
+    if (dummy) {
+      // Appendix B: a column for the dummy center, (largest entry + 1) for every unit
+      if ((e = dalloc(&cm_ext, nk, h->st)) != hipSuccess || (e = dalloc(&mx, 1, h->st)) != hipSuccess) {
+        rc = hip_fail(e, "device allocation"); break;
+      }
+      if ((e = hipMemcpyAsync(mx, &mx_h, 4, hipMemcpyHostToDevice, h->st)) != hipSuccess ||
+          (e = lbdd::launch_extend_dummy(k_user, n, cm_dev, cm_ext, mx, h->st)) != hipSuccess ||
+          (e = hipMemcpyAsync(&mx_h, mx, 4, hipMemcpyDeviceToHost, h->st)) != hipSuccess) {
+        rc = hip_fail(e, "dummy center"); break;
+      }
+      cm_dev = cm_ext;
     }
     if ((e = hipMallocAsync(&work, lbdd::setup_work_bytes(k, n), h->st)) != hipSuccess) { rc = hip_fail(e, "device allocation"); break; }
     if ((e = dalloc(&bad, 1, h->st)) != hipSuccess) { rc = hip_fail(e, "device allocation"); break; }
@@ -171,14 +207,39 @@ int lbdd_create(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity
         (e = hipStreamSynchronize(h->st)) != hipSuccess) {
       rc = hip_fail(e, "setup"); break;
     }
-    if (bad_h) rc = fail(LBDD_E_INVAL, "cost matrix has an entry outside [0, 2^30)");
+    if (bad_h) rc = fail(LBDD_E_INVAL, dummy ? "cost matrix has an entry outside [0, 2^30 - 1) (the dummy "
+                                               "center costs one more than the largest)"
+                                             : "cost matrix has an entry outside [0, 2^30)");
+    h->dummy_cost = (int64_t)mx_h + 1;
   } while (0);
   (void)hipStreamSynchronize(h->st);
   if (cm_tmp) (void)hipFreeAsync(cm_tmp, h->st);
+  if (cm_ext) (void)hipFreeAsync(cm_ext, h->st);
+  if (mx) (void)hipFreeAsync(mx, h->st);
   if (work) (void)hipFreeAsync(work, h->st);
   if (bad) (void)hipFreeAsync(bad, h->st);
   if (rc != LBDD_OK) { release(h); return rc; }
   *out = h;
+  return LBDD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbdd_create(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity,
+                const int32_t *penalty, uint32_t flags, void *hip_stream, lbdd_instance **out) {
+  return create_instance(k, n, cm, capacity, penalty, flags, hip_stream, false, out);
+}
+
+int lbdd_create_strict(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity,
+                       uint32_t flags, void *hip_stream, lbdd_instance **out) {
+  return create_instance(k, n, cm, capacity, nullptr, flags, hip_stream, true, out);
+}
+
+int lbdd_centers(lbdd_instance *h, int32_t *k_graph) {
+  if (!h || !k_graph) return fail(LBDD_E_INVAL, "NULL argument");
+  *k_graph = h->k;
   return LBDD_OK;
 }
 
@@ -224,7 +285,15 @@ int lbdd_objective(lbdd_instance *h, int64_t *out) {
   int64_t sc[lbdd::SC_COUNT];
   int rc = read_scalars(h, sc);
   if (rc) return rc;
-  *out = sc[lbdd::SC_OBJECTIVE];
+  int64_t obj = sc[lbdd::SC_OBJECTIVE];
+  if (h->dummy >= 0) {
+    // Equation (3) counts the allotted units only: the dummy center's cost,
+    // the same for every complete allotment, is taken out again
+    int32_t at_dummy = 0;
+    HIP_TRY(copy_sync(&at_dummy, h->load + h->dummy, 4, hipMemcpyDeviceToHost, h->st), "copy load");
+    obj -= (int64_t)at_dummy * h->dummy_cost;
+  }
+  *out = obj;
   return LBDD_OK;
 }
 
@@ -240,7 +309,7 @@ int lbdd_assignment(lbdd_instance *h, int32_t *out, uint32_t flags) {
   if (!h || !out) return fail(LBDD_E_INVAL, "NULL argument");
   if (flags & ~LBDD_OUT_DEVICE) return fail(LBDD_E_INVAL, "unknown flags 0x%x", flags);
   int32_t *dst = (flags & LBDD_OUT_DEVICE) ? out : h->unperm;
-  HIP_TRY(lbdd::launch_unpermute(h->n, h->order, h->assign, dst, h->st), "unpermute kernel");
+  HIP_TRY(lbdd::launch_unpermute(h->n, h->order, h->assign, h->dummy, dst, h->st), "unpermute kernel");
   int64_t sc[lbdd::SC_COUNT];
   int rc = read_scalars(h, sc);
   if (rc) return rc;

@@ -16,8 +16,12 @@ int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 }  // namespace lbdd
 
 struct lbdd_instance {
-  int32_t k = 0;
+  int32_t k = 0;                        // centers of the graph (strict: + the dummy center)
   int64_t n = 0;
+  bool strict = false;                  // a strict-LBDD instance (Appendix B)
+  int32_t k_user = 0;                   // centers given by the caller
+  int32_t dummy = -1;                   // index of the dummy center, -1 if none
+  int64_t dummy_cost = 0;               // its cost for every unit (largest entry + 1)
   hipStream_t st = nullptr;
   int64_t enqueued = 0;                 // iterations launched so far
   int32_t *cm = nullptr, *smin = nullptr, *cap = nullptr, *pen = nullptr;
@@ -32,7 +36,7 @@ struct lbdd_instance {
 
   lbdd::InstView view() const {
     lbdd::InstView v;
-    v.k = k; v.n = n; v.cm = cm; v.smin = smin; v.cap = cap; v.pen = pen;
+    v.k = k; v.strict = strict ? 1 : 0; v.n = n; v.cm = cm; v.smin = smin; v.cap = cap; v.pen = pen;
     v.assign = assign; v.load = load; v.members = members; v.slot = slot; v.W = W; v.Wh = Wh;
     v.best = best; v.meta = meta; v.thr = thr;
     v.scalars = scalars;

@@ -25,6 +25,12 @@ __device__ __host__ inline int32_t key_delta(uint64_t key) {
 }
 __device__ __host__ inline uint32_t key_rank(uint64_t key) { return (uint32_t)key; }
 
+// Key of a zero-cost dummy-unit transfer of strict-LBDD (Appendix B): a
+// center with free capacity holds dummy units that can move to any other
+// center at no cost.  Its rank field lies beyond every real row, so it
+// orders after every real key of cost 0; moving it moves no real unit.
+constexpr uint64_t DUMMY_KEY = (uint64_t)0x80000000u << 32 | 0xfffffffeu;
+
 // Bias that makes a search label (a sum of at most LBDD_MAX_K+1 edges of
 // magnitude < 2^31) non-negative, so labels order as unsigned integers.
 constexpr int64_t DIST_BIAS = 1ll << 46;
@@ -33,6 +39,9 @@ constexpr int64_t DIST_BIAS = 1ll << 46;
 // the unit processed in iteration r, so a best-transfer key's rank is the row.
 struct InstView {
   int32_t k;
+  int32_t strict;          // strict-LBDD: W[u][v] includes the dummy transfer
+                           // while u has free capacity; allotment goes to the
+                           // cheapest center with free capacity
   int64_t n;
   const int32_t *cm;       // [n][k] permuted cost matrix
   const int32_t *smin;     // [n] most suitable center of row r
@@ -127,8 +136,13 @@ hipError_t launch_setup(int32_t k, int64_t n, const int32_t *cm_in, int32_t *cm_
 // solve.hip: iterations [r_begin, r_end) of the main loop
 hipError_t launch_init_state(const InstView &I, hipStream_t st);
 hipError_t launch_solve(const InstView &I, int64_t r_begin, int64_t r_end, hipStream_t st);
-hipError_t launch_unpermute(int64_t n, const int64_t *order, const int32_t *assign, int32_t *out,
-                            hipStream_t st);
+hipError_t launch_unpermute(int64_t n, const int64_t *order, const int32_t *assign, int32_t dummy,
+                            int32_t *out, hipStream_t st);
+// setup.hip: the cost matrix of a strict-LBDD instance with excess demand,
+// extended by a dummy center whose column holds (largest entry + 1); *mx
+// receives the largest entry (it must hold 0 before the call)
+hipError_t launch_extend_dummy(int32_t k, int64_t n, const int32_t *cm, int32_t *cm_ext, int32_t *mx,
+                               hipStream_t st);
 size_t batch_lds_bytes(const BatchItem *items_host, int32_t m);
 int batch_workers(size_t lds_bytes, int32_t m);
 hipError_t launch_solve_batch(const BatchItem *items_dev, int32_t m, int32_t *head, size_t lds_bytes,

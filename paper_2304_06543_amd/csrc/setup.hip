@@ -141,7 +141,43 @@ __global__ __launch_bounds__(256) void permute_rows_kernel(int32_t k, int64_t n,
 
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Largest entry of the cost matrix (strict-LBDD with excess demand, Appendix
+// B: the dummy center costs one more than it for every unit).
+__global__ __launch_bounds__(256) void cm_max_kernel(int64_t count, const int32_t *__restrict__ cm,
+                                                     int32_t *__restrict__ mx) {
+  int32_t m = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    m = max(m, cm[i]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(mx, m);
+}
+
+// cm_ext [n][k+1]: the k given columns, then the dummy center's column.
+__global__ __launch_bounds__(256) void extend_dummy_kernel(int32_t k, int64_t n,
+                                                           const int32_t *__restrict__ cm,
+                                                           const int32_t *__restrict__ mx,
+                                                           int32_t *__restrict__ out) {
+  const int64_t k1 = (int64_t)k + 1;
+  const int32_t dummy = *mx + 1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n * k1; i += stride) {
+    const int64_t d = i / k1, j = i - d * k1;
+    out[i] = j < k ? cm[d * k + j] : dummy;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_extend_dummy(int32_t k, int64_t n, const int32_t *cm, int32_t *cm_ext, int32_t *mx,
+                               hipStream_t st) {
+  cm_max_kernel<<<2048, 256, 0, st>>>(n * (int64_t)k, cm, mx);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  extend_dummy_kernel<<<4096, 256, 0, st>>>(k, n, cm, mx, cm_ext);
+  return hipGetLastError();
+}
 
 size_t setup_work_bytes(int32_t k, int64_t n) {
   (void)k;

@@ -26,6 +26,12 @@
 // (label, node) pairs are packed so that one unsigned min keeps the smallest
 // label and, on ties, the smallest predecessor node.
 //
+// Strict-LBDD (Appendix B, Algorithm 4) runs the same loop: the unit goes to
+// the cheapest center that still has free capacity, only Negative Cycle
+// Refinement follows, and W[u][v] also holds the zero-cost dummy transfer
+// (DUMMY_KEY) while u has free capacity, so the searches see the dummy units
+// without knowing of them; applying a dummy transfer moves no unit.
+//
 // One workgroup of 1024 threads owns the instance.  W lives in LDS when it
 // fits (k <= ~135) and in global memory (L2-resident) otherwise.
 #include "lbdd_dev.hpp"
@@ -415,6 +421,14 @@ __device__ __forceinline__ void retry_potential(const InstView &I, const Lds &L,
   __syncthreads();
 }
 
+// Strict-LBDD: W[u][v] from the head of the list of (u, v) and the dummy
+// transfer while u has free capacity (the loads in LDS are current).
+__device__ __forceinline__ uint64_t strict_entry(const InstView &I, const Lds &L, int u, int v) {
+  if (u == v) return KEY_NONE;
+  const uint64_t head = I.best[((int64_t)u * I.k + v) * BEST_M];
+  return L.load[u] < L.cap[u] ? umin(head, DUMMY_KEY) : head;
+}
+
 // Label of a center during a search, packed so that one unsigned min orders
 // by (distance, edges, predecessor): ((dist + 2^41) << 22) | (edges << 11) |
 // pred.  Simple paths have at most k - 1 <= 2047 edges of |delta| < 2^30, so
@@ -788,15 +802,20 @@ __device__ __forceinline__ bool refine(const InstView &I, const Lds &L, Scalars 
     const bool bad = v != -1 || len < 2 || path[len - 1] != s;
     if (bad) { S.status = -5; len = 1; }
     const int nedges = len - 1;
-    const int nmov = mode == 0 ? nedges : nedges - 1;
-    // read every moved unit before any move
-    for (int e = 0; e < nmov; ++e) {
+    const int ntrans = mode == 0 ? nedges : nedges - 1;
+    // read every moved unit before any move; a dummy transfer (strict-LBDD
+    // only) moves no real unit
+    int nmov = 0;
+    for (int e = 0; e < ntrans; ++e) {
       const int u = path[len - 1 - e];
       int v = path[len - 2 - e];
       if (v == k) v = s;
-      L.mrow[e] = (int32_t)key_rank(L.W[(int64_t)u * k + v]);
-      L.mfrom[e] = u;
-      L.mto[e] = v;
+      const uint64_t key = L.W[(int64_t)u * k + v];
+      if (key == DUMMY_KEY) continue;
+      L.mrow[nmov] = (int32_t)key_rank(key);
+      L.mfrom[nmov] = u;
+      L.mto[nmov] = v;
+      ++nmov;
     }
     for (int e = 0; e < nmov; ++e) {
       const int x = L.mrow[e], u = L.mfrom[e], v = L.mto[e];
@@ -827,10 +846,43 @@ __device__ __forceinline__ bool refine(const InstView &I, const Lds &L, Scalars 
   // lists left unknown are refilled from the final members
   move_lists(I, L, nmov);
   refill_moved(I, L, S, nmov);
+  if (I.strict) {
+    // the moves changed the loads of their centers and no other: their rows
+    // take the list heads and the dummy transfers again
+    for (int64_t t = tid; t < (int64_t)2 * nmov * k; t += NT) {
+      const int j = (int)(t / k), w = (int)(t - (int64_t)j * k);
+      const int u = (j & 1) ? L.mto[j >> 1] : L.mfrom[j >> 1];
+      set_w(L, (int64_t)u * k + w, strict_entry(I, L, u, w));
+    }
+  }
   if (tid == 0) S.stats[ST_T_RESCAN] += now() - t0;
   __syncthreads();
   if (S.status == 0) retry_potential(I, L, S, s, nmov);
   return false;
+}
+
+// Strict-LBDD allotment (Algorithm 4): the center with free capacity of the
+// smallest cost for this unit, smallest index among equal costs.  Every
+// thread returns it.  Some center always has room while units remain (the
+// capacities, with the dummy center's, sum to at least n); if none has, the
+// status records the failed invariant and `fallback` is returned.
+__device__ __forceinline__ int strict_center(const InstView &I, const Lds &L, Scalars &S,
+                                             const int32_t *row, int fallback) {
+  const int k = I.k;
+  uint64_t b = KEY_NONE;
+  for (int t = threadIdx.x; t < k; t += NT)
+    if (L.load[t] < L.cap[t]) b = umin(b, (uint64_t)(uint32_t)row[t] << 32 | (uint32_t)t);
+  b = wave_min_u64(b);
+  if ((threadIdx.x & 63) == 0) L.wmin[threadIdx.x >> 6] = b;
+  __syncthreads();
+  uint64_t g = KEY_NONE;
+#pragma unroll
+  for (int j = 0; j < NT / 64; ++j) g = umin(g, L.wmin[j]);
+  if (g == KEY_NONE) {
+    if (threadIdx.x == 0) S.status = -5;
+    return fallback;
+  }
+  return (int)(uint32_t)g;
 }
 
 // Layout of the dynamic LDS of one solving workgroup (solve_lds_bytes).
@@ -899,8 +951,16 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
       // the next barrier), scaled by 8
       const bool timed = tid == 0 && (r & 7) == 0;
       const int64_t t0 = timed ? now() : 0;
-      const int s = I.smin[r];
       const int32_t *row = I.cm + r * k;
+      int s = I.smin[r];
+      if (I.strict) {
+        // strict-LBDD: the cheapest center with free capacity (the most
+        // suitable one whenever it has room); every thread reads the load
+        // before thread 0 changes it below
+        const bool full = L.load[s] >= L.cap[s];
+        __syncthreads();
+        if (full) s = strict_center(I, L, S, row, s);
+      }
       if (tid == 0) {
         const int ld = L.load[s];
         const int vac = ld < L.cap[s];
@@ -912,6 +972,11 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
         S.obj += (int64_t)row[s] + (vac ? 0 : L.pen[s]);
       }
       const int ins = join_center(I, L, S, (int)r, s, (int)(r & 1));   // contains a barrier
+      if (I.strict && L.load[s] == L.cap[s]) {
+        // s has just become full: its dummy transfers are gone
+        for (int v = tid; v < k; v += NT) set_w(L, (int64_t)s * k + v, strict_entry(I, L, s, v));
+        __syncthreads();
+      }
       const int64_t t1 = timed ? now() : 0;
       // Negative Cycle Refinement can only find something if the current W
       // may hold a negative cycle: the insert lowered an entry and the node
@@ -989,8 +1054,11 @@ __global__ void init_state_kernel(InstView I) {
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = t0; i < I.n; i += stride) I.assign[i] = -1;
   for (int64_t i = t0; i < (int64_t)I.k * I.k; i += stride) {
-    I.W[i] = KEY_NONE;
-    I.Wh[i] = 0xffffffffu;
+    // strict-LBDD: every center with capacity starts full of dummy units
+    const int u = (int)(i / I.k), v = (int)(i - (int64_t)u * I.k);
+    const uint64_t w0 = (I.strict && u != v && I.cap[u] > 0) ? DUMMY_KEY : KEY_NONE;
+    I.W[i] = w0;
+    I.Wh[i] = (uint32_t)(w0 >> 32);
     I.meta[i] = META_ALL;                       // empty center: every unit (none) held
     I.thr[i] = KEY_NONE;                        // ... so every joining unit enters
   }
@@ -999,11 +1067,17 @@ __global__ void init_state_kernel(InstView I) {
   for (int64_t i = t0; i < SC_COUNT; i += stride) I.scalars[i] = 0;
 }
 
-// out[order[r]] = assign[r]: back from processing order to the caller's order
+// out[order[r]] = assign[r]: back from processing order to the caller's
+// order, with -1 for a unit at the dummy center of strict-LBDD (dummy = -1
+// when there is none).
 __global__ void unpermute_kernel(int64_t n, const int64_t *__restrict__ order,
-                                 const int32_t *__restrict__ assign, int32_t *__restrict__ out) {
+                                 const int32_t *__restrict__ assign, int32_t dummy,
+                                 int32_t *__restrict__ out) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < n) out[order[r]] = assign[r];
+  if (r < n) {
+    const int32_t a = assign[r];
+    out[order[r]] = (a == dummy) ? -1 : a;
+  }
 }
 
 }  // namespace
@@ -1013,9 +1087,9 @@ hipError_t launch_init_state(const InstView &I, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_unpermute(int64_t n, const int64_t *order, const int32_t *assign, int32_t *out,
-                            hipStream_t st) {
-  unpermute_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, order, assign, out);
+hipError_t launch_unpermute(int64_t n, const int64_t *order, const int32_t *assign, int32_t dummy,
+                            int32_t *out, hipStream_t st) {
+  unpermute_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, order, assign, dummy, out);
   return hipGetLastError();
 }
 

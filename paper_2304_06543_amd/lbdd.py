@@ -35,7 +35,7 @@ EXPORTS = ("lbdd_create", "lbdd_solve", "lbdd_solve_iters", "lbdd_solve_batch", 
            "lbdd_best_transfers", "lbdd_server_create", "lbdd_server_submit",
            "lbdd_server_poll", "lbdd_server_wait", "lbdd_server_result", "lbdd_server_stats",
            "lbdd_server_destroy", "lbdd_set_option", "lbdd_get_option", "lbdd_tune_search",
-           "lbdd_tune_best_transfers")
+           "lbdd_tune_best_transfers", "lbdd_create_strict", "lbdd_centers")
 JOB_QUEUED, JOB_RUNNING, JOB_DONE = 0, 1, 2
 SERVER_STATS = ("submitted", "admitted", "finished", "failed", "kernel_launches",
                 "peak_jobs", "peak_bytes", "bytes_now", "workers")
@@ -83,6 +83,8 @@ def load(path: str = LIB_PATH):
         "lbdd_get_option": ([P, I32, C.POINTER(I64)], C.c_int),
         "lbdd_tune_search": ([I32, I64, P, P, P, U32, I64, P, C.POINTER(I64), P, I32], C.c_int),
         "lbdd_tune_best_transfers": ([I32, I64, P, P, P, P, P, I32, P, P, P], C.c_int),
+        "lbdd_create_strict": ([I32, I64, P, P, U32, P, C.POINTER(P)], C.c_int),
+        "lbdd_centers": ([P, C.POINTER(I32)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -139,17 +141,33 @@ def _create_args(cm, capacity, penalty):
 class Instance:
     """One LBDD instance living on the GPU (lbdd_create ... lbdd_destroy)."""
 
-    def __init__(self, cm, capacity, penalty, stream=None):
+    def __init__(self, cm, capacity, penalty=None, stream=None, strict: bool = False):
+        """penalty is required unless strict (strict-LBDD, lbdd_create_strict,
+        which takes none)."""
         lib = load()
         self._lib = lib
         self._h = C.c_void_p()
-        k, n, ptr, flags, cap, pen, keep = _create_args(cm, capacity, penalty)
-        self.k, self.n = k, n
+        if strict:
+            if penalty is not None:
+                raise ValueError("strict-LBDD takes no penalties")
+            k, n, ptr, flags, cap, _, keep = _create_args(cm, capacity, capacity)
+        else:
+            if penalty is None:
+                raise ValueError("penalty is required")
+            k, n, ptr, flags, cap, pen, keep = _create_args(cm, capacity, penalty)
+        self.k, self.n, self.strict = k, n, strict
         self._stream = _stream_ptr(stream)
-        _check(lib.lbdd_create(k, n, ptr, cap.ctypes.data_as(C.c_void_p),
-                               pen.ctypes.data_as(C.c_void_p), flags, self._stream,
-                               C.byref(self._h)))
+        if strict:
+            _check(lib.lbdd_create_strict(k, n, ptr, cap.ctypes.data_as(C.c_void_p), flags,
+                                          self._stream, C.byref(self._h)))
+        else:
+            _check(lib.lbdd_create(k, n, ptr, cap.ctypes.data_as(C.c_void_p),
+                                   pen.ctypes.data_as(C.c_void_p), flags, self._stream,
+                                   C.byref(self._h)))
         del keep
+        kg = C.c_int32()
+        _check(lib.lbdd_centers(self._h, C.byref(kg)))
+        self.k_graph = int(kg.value)    # k, or k + 1 with strict-LBDD's dummy center
 
     def set_option(self, option: int, value: int):
         _check(self._lib.lbdd_set_option(self._h, int(option), int(value)))
@@ -191,9 +209,9 @@ class Instance:
         return out
 
     def snapshot(self):
-        """(load[k], W[k][k] uint64 keys, order[n])."""
-        load_ = np.empty(self.k, np.int32)
-        W = np.empty((self.k, self.k), np.uint64)
+        """(load[kg], W[kg][kg] uint64 keys, order[n]) with kg = k_graph."""
+        load_ = np.empty(self.k_graph, np.int32)
+        W = np.empty((self.k_graph, self.k_graph), np.uint64)
         order = np.empty(self.n, np.int64)
         _check(self._lib.lbdd_snapshot(self._h, load_.ctypes.data_as(C.c_void_p),
                                        W.ctypes.data_as(C.c_void_p),
@@ -226,6 +244,15 @@ class Instance:
 def solve(cm, capacity, penalty, stream=None):
     """Solve one instance; returns (objective, assignment as numpy int32)."""
     with Instance(cm, capacity, penalty, stream) as inst:
+        inst.solve()
+        return inst.objective(), inst.assignment()
+
+
+def solve_strict(cm, capacity, stream=None):
+    """Solve one strict-LBDD instance (Appendix B); returns (objective of
+    Equation (3), assignment as numpy int32 with -1 for units no center can
+    hold)."""
+    with Instance(cm, capacity, stream=stream, strict=True) as inst:
         inst.solve()
         return inst.objective(), inst.assignment()
 

@@ -39,6 +39,22 @@ def main():
                             "bf_rounds", "heap_pushes", "iterations"], r.stats.tolist())),
             oracle_seconds=round(dt, 2))
         print(name, res[name]["objective"], dt, flush=True)
+    # strict-LBDD (Appendix B) on the same capacities: excess demand, so the
+    # dummy center takes n - sum(capacity) units
+    for name in ("C1", "C2"):
+        inst = L.make_config(name)
+        t = time.time()
+        r = oracle.solve_strict(inst.cm, inst.cap)
+        dt = time.time() - t
+        res[name + "_strict"] = dict(
+            k=inst.k, n=inst.n, input_sha256=L.input_hash(inst), objective=r.objective,
+            assignment_sha256=assignment_hash(r.assign), kx=r.kx,
+            unallotted=int((r.assign < 0).sum()),
+            load=r.load.tolist() if r.kx <= 129 else None,
+            stats=dict(zip(["cycles", "paths", "moves", "cycle_searches", "path_searches",
+                            "bf_rounds", "heap_pushes", "iterations"], r.stats.tolist())),
+            oracle_seconds=round(dt, 2))
+        print(name + "_strict", r.objective, dt, flush=True)
     with open(OUT, "w") as f:
         json.dump(res, f, indent=1)
 

@@ -89,3 +89,23 @@ def test_strict_dummy_key_orders_after_real_keys_of_equal_cost():
     one_real = np.uint64(((2**31 + 1) << 32) | 0)           # cost 1, rank 0
     assert zero_real < oracle.DUMMY_KEY < one_real
     assert int(oracle.key_delta(np.array([oracle.DUMMY_KEY]))[0]) == 0
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_strict_no_negative_cycle_after_every_iteration(seed):
+    """Lemma 2 carried to strict-LBDD: each allotment lowers only the anchor's
+    row, so one Negative Cycle Refinement from it leaves no negative cycle.
+    Checked after every iteration of a small run, and the objective of every
+    prefix is the optimum of the units allotted so far (Theorem 2 on the
+    prefix: the same capacities, the first r units of the order)."""
+    rng = np.random.default_rng(40 + seed)
+    k, n = 2 + seed % 5, 24
+    cm = rng.integers(0, [4, 30, 200][seed % 3], size=(n, k)).astype(np.int32)
+    cap = rng.integers(0, 2 * n // k, size=k).astype(np.int32)
+    _, _, order, _ = oracle.setup(cm)
+    for r in range(1, n + 1):
+        res = oracle.solve_strict(cm, cap, max_iters=r, want_W=True)
+        assert not pins.has_negative_cycle(res.W), r
+        sub = cm[order[:r]]
+        if int(cap.sum()) >= r:
+            assert res.objective == pins.opt_strict(sub, cap), r
