@@ -54,8 +54,11 @@ def _load(path: str = LIB):
     lib.orc_refine_search.argtypes = [C.c_int32, P, C.c_int32, C.c_int32, P, P, P, P, P, P]
     lib.orc_solve.argtypes = [C.c_int32, C.c_int64, P, P, P, C.c_int64, P, P, P, P, P, P]
     lib.orc_solve_strict.argtypes = [C.c_int32, C.c_int64, P, P, C.c_int64, P, P, P, P, P, P]
+    lib.orc_solve_q.argtypes = [C.c_int32, C.c_int64, P, P, P, P, C.c_int64, P, P, P, P, P, P]
+    lib.orc_refine_search_q.argtypes = [C.c_int32, P, C.c_int32, C.c_int32, P, P, P, P, P, P, P]
     for f in (lib.orc_setup, lib.orc_best_transfers, lib.orc_objective,
-              lib.orc_refine_search, lib.orc_solve, lib.orc_solve_strict):
+              lib.orc_refine_search, lib.orc_solve, lib.orc_solve_strict, lib.orc_solve_q,
+              lib.orc_refine_search_q):
         f.restype = C.c_int
     if path == LIB:
         _lib = lib
@@ -130,6 +133,21 @@ def refine_search(W: np.ndarray, anchor: int, mode: int, load, cap, pen, lib=Non
     return dist, pred, int(rounds[0])
 
 
+def refine_search_q(W: np.ndarray, anchor: int, mode: int, load, cap, pen_off, pen_val, lib=None):
+    """refine_search with a penalty table per center (see solve_q)."""
+    lib = lib or _load()
+    W = np.ascontiguousarray(W, dtype=np.uint64)
+    k = W.shape[0]
+    dist = np.empty(k + 1, np.int64); pred = np.empty(k + 1, np.int32)
+    rounds = np.zeros(1, np.int32)
+    off = np.ascontiguousarray(pen_off, dtype=np.int64)
+    rc = lib.orc_refine_search_q(k, _p(W), anchor, mode, _p(_i32(load)), _p(_i32(cap)),
+                                 _p(off), _p(_i32(pen_val)), _p(dist), _p(pred), _p(rounds))
+    if rc:
+        raise OracleError(rc, "orc_refine_search_q")
+    return dist, pred, int(rounds[0])
+
+
 @dataclass
 class Result:
     assign: np.ndarray      # int32 [n], center per unit id (-1: not allotted)
@@ -199,3 +217,27 @@ def key_delta(W: np.ndarray) -> np.ndarray:
 
 def key_rank(W: np.ndarray) -> np.ndarray:
     return (W & np.uint64(0xFFFFFFFF)).astype(np.int64)
+
+
+def solve_q(cm, cap, pen_off, pen_val, max_iters: int = -1, want_W: bool = False,
+            want_trace: bool = False, lib=None) -> Result:
+    """ASRAL with a general penalty function (Definition of the penalty
+    function, Section 2): the j-th unit beyond the capacity of center s pays
+    pen_val[pen_off[s] + min(j, len_s) - 1], len_s = pen_off[s+1] - pen_off[s]
+    >= 1 (the last value of a center's table holds for every later unit)."""
+    lib = lib or _load()
+    cm = _i32(cm)
+    n, k = cm.shape
+    iters = n if (max_iters < 0 or max_iters > n) else max_iters
+    assign = np.empty(n, np.int32); load = np.empty(k, np.int32)
+    obj = np.zeros(1, np.int64)
+    W = np.empty((k, k), np.uint64) if want_W else None
+    trace = np.zeros((max(iters, 1), TRACE_W), np.int64) if want_trace else None
+    stats = np.zeros(STATS_N, np.int64)
+    off = np.ascontiguousarray(pen_off, dtype=np.int64)
+    rc = lib.orc_solve_q(k, n, _p(cm), _p(_i32(cap)), _p(off), _p(_i32(pen_val)), iters,
+                         _p(assign), _p(load), _p(obj), _p(W) if W is not None else None,
+                         _p(trace) if trace is not None else None, _p(stats))
+    if rc:
+        raise OracleError(rc, "orc_solve_q")
+    return Result(assign, load, int(obj[0]), W, trace[:iters] if trace is not None else None, stats)

@@ -22,21 +22,28 @@
  *                        Refinement (Algorithm 1) and Negative Path Refinement
  *                        (Appendix A), keeping Gamma in one min-heap per
  *                        ordered pair of centers ("BestTransHeap", Section 3.5).
+ *   orc_solve_q          the same loop with a general penalty function per
+ *                        center (Definition of the penalty function, Section
+ *                        2), given as a table of the penalties of successive
+ *                        units beyond capacity.
  *   orc_objective        the objective of Equation (1) with one constant
  *                        per-unit penalty per center.
  *
  * Readings where the paper leaves a choice (each is listed in the design notes):
  *   - vacancy of s_j is "load before adding d_i < capacity", computed from loads;
  *   - penalty q_s(j) is one constant per center for every unit beyond capacity
- *     (the paper's experiments);
+ *     (the paper's experiments) in orc_solve; orc_solve_q takes any
+ *     non-decreasing q_s(j) as a table whose last value holds for every later j;
  *   - ties: most suitable center = smallest index among equal costs; the
  *     processing order sorts by (cheapest cost, unit id); the best transfer of a
  *     pair is the smallest transfer cost, then the smallest processing rank;
  *     Bellman-Ford runs in synchronous rounds, a label changes only on strict
  *     improvement and its predecessor is the smallest node index achieving it;
  *   - a refinement is applied only when its cost is strictly negative;
- *   - the penalty edge u -> s*_in costs (load[u] >= cap[u] ? pen[u] : 0) -
- *     pen[s*]; the path's penalty edge is added to the objective once;
+ *   - the penalty edge u -> s*_in costs (penalty the next unit at u would pay)
+ *     - (penalty of the anchor's last unit beyond capacity): with a constant
+ *     penalty (load[u] >= cap[u] ? pen[u] : 0) - pen[s*]; the path's penalty
+ *     edge is added to the objective once;
  *   - the transfer cost sign follows the definition of Gamma (cost of moving dn
  *     from s_i to s_j is CM(dn,s_j) - CM(dn,s_i)).
  *
@@ -77,6 +84,36 @@ static inline int64_t key_delta(uint64_t key) {
 }
 static inline int64_t key_rank(uint64_t key) { return (int64_t)(key & 0xffffffffu); }
 
+/* Penalty function of every center (Definition of the penalty function,
+ * Section 2): the j-th unit (j >= 1) beyond the capacity of center s pays
+ * val[off[s] + min(j, len_s) - 1], len_s = off[s+1] - off[s] >= 1, so the
+ * last value of a center's table holds for every later unit.  A constant
+ * penalty per center is a table of one value per center.                    */
+typedef struct { const int64_t *off; const int32_t *val; } pen_table;
+
+static int64_t q_at(const pen_table *P, int32_t s, int64_t j) {
+    const int64_t len = P->off[s + 1] - P->off[s];
+    return P->val[P->off[s] + (j < len ? j : len) - 1];
+}
+/* what the next unit allotted to u pays on top of its cost (0 while u has room) */
+static int64_t q_next(const pen_table *P, const int32_t *load, const int32_t *cap, int32_t u) {
+    return load[u] >= cap[u] ? q_at(P, u, (int64_t)load[u] - cap[u] + 1) : 0;
+}
+/* what the last unit beyond the anchor's capacity pays.  The anchor is
+ * overloaded whenever a path search runs in the solve; a standalone search on
+ * an anchor within capacity takes the first unit's penalty (with a constant
+ * penalty: pen[s*] in every case).                                           */
+static int64_t q_last(const pen_table *P, const int32_t *load, const int32_t *cap, int32_t u) {
+    return q_at(P, u, load[u] > cap[u] ? (int64_t)load[u] - cap[u] : 1);
+}
+
+/* A table of one value per center holding pen[]; off has k + 1 entries.     */
+static void flat_table(int32_t k, const int32_t *pen, int64_t *off, pen_table *P) {
+    for (int32_t s = 0; s <= k; ++s) off[s] = s;
+    P->off = off;
+    P->val = pen;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Input validation: k >= 1, n >= 1, 0 <= CM < 2^30, cap >= 0, pen >= 1.     */
 static int validate(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap,
@@ -88,6 +125,22 @@ static int validate(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap,
         for (int32_t s = 0; s < k; ++s) if (cap[s] < 0) return ORC_E_INVAL;
     if (pen)
         for (int32_t s = 0; s < k; ++s) if (pen[s] < 1 || pen[s] >= CM_LIMIT) return ORC_E_INVAL;
+    return ORC_OK;
+}
+
+/* Penalty tables: off[0] = 0, at least one value per center, every value in
+ * [1, 2^30), non-decreasing within a center (the definition asks for an
+ * increasing function; equal successive values keep the constant penalty of
+ * the experiments inside the family).                                        */
+static int validate_table(int32_t k, const int64_t *off, const int32_t *val) {
+    if (!off || !val || off[0] != 0) return ORC_E_INVAL;
+    for (int32_t s = 0; s < k; ++s) {
+        if (off[s + 1] <= off[s]) return ORC_E_INVAL;
+        for (int64_t i = off[s]; i < off[s + 1]; ++i) {
+            if (val[i] < 1 || val[i] >= CM_LIMIT) return ORC_E_INVAL;
+            if (i > off[s] && val[i] < val[i - 1]) return ORC_E_INVAL;
+        }
+    }
     return ORC_OK;
 }
 
@@ -183,13 +236,13 @@ int orc_objective(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap,
  *   s*_out -> v:                            W[s*][v]
  *   u -> s*_in:                             W[u][s*]
  * NPath (Definition in Section 3.4): as NCyc, but every edge into s*_in is the
- *   penalty difference q_u() - q_s*() with q_u() = pen[u] if u is at or beyond
- *   capacity (one more unit there is penalised) and 0 otherwise, and
- *   q_s*() = pen[s*] (the anchor is overloaded whenever this graph is built).
+ *   penalty difference q_u() - q_s*(): q_u() is what one more unit at u would
+ *   pay (0 while u has room), q_s*() what the anchor's last unit beyond its
+ *   capacity pays (the anchor is overloaded whenever this graph is built).
  * Pairs with no unit to transfer have no edge; there are no self loops, no
  * edges into s*_out and none out of s*_in.                                    */
 static void build_split_graph(int32_t k, const uint64_t *W, int32_t anchor, int mode,
-                              const int32_t *load, const int32_t *cap, const int32_t *pen,
+                              const int32_t *load, const int32_t *cap, const pen_table *P,
                               int64_t *wt, uint8_t *has) {
     const int32_t K1 = k + 1;
     memset(has, 0, (size_t)K1 * K1);
@@ -209,8 +262,7 @@ static void build_split_graph(int32_t k, const uint64_t *W, int32_t anchor, int 
                 has[(int64_t)u * K1 + k] = 1;
             }
         } else {
-            int64_t qu = (load[u] >= cap[u]) ? pen[u] : 0;
-            wt[(int64_t)u * K1 + k] = qu - pen[anchor];
+            wt[(int64_t)u * K1 + k] = q_next(P, load, cap, u) - q_last(P, load, cap, anchor);
             has[(int64_t)u * K1 + k] = 1;
         }
     }
@@ -247,21 +299,37 @@ static int bellman_ford(int32_t K1, int32_t src, const int64_t *wt, const uint8_
 }
 
 /* Search entry used by tests: builds the split graph for (W, anchor, mode) and
- * returns dist/pred over the k+1 nodes and the number of rounds.              */
-int orc_refine_search(int32_t k, const uint64_t *W, int32_t anchor, int32_t mode,
-                      const int32_t *load, const int32_t *cap, const int32_t *pen,
-                      int64_t *dist, int32_t *pred, int32_t *rounds) {
+ * returns dist/pred over the k+1 nodes and the number of rounds.  The penalty
+ * is a table (orc_refine_search_q) or one constant per center.                */
+int orc_refine_search_q(int32_t k, const uint64_t *W, int32_t anchor, int32_t mode,
+                        const int32_t *load, const int32_t *cap, const int64_t *pen_off,
+                        const int32_t *pen_val, int64_t *dist, int32_t *pred, int32_t *rounds) {
     if (k < 1 || anchor < 0 || anchor >= k) return ORC_E_INVAL;
+    if (validate_table(k, pen_off, pen_val)) return ORC_E_INVAL;
+    const pen_table P = {pen_off, pen_val};
     const int32_t K1 = k + 1;
     int64_t *wt = (int64_t *)malloc(sizeof(int64_t) * (size_t)K1 * K1);
     uint8_t *has = (uint8_t *)malloc((size_t)K1 * K1);
     int64_t *scratch = (int64_t *)malloc(sizeof(int64_t) * (size_t)K1);
     int rc = ORC_E_NOMEM;
     if (wt && has && scratch) {
-        build_split_graph(k, W, anchor, mode, load, cap, pen, wt, has);
+        build_split_graph(k, W, anchor, mode, load, cap, &P, wt, has);
         rc = bellman_ford(K1, anchor, wt, has, dist, pred, scratch, rounds);
     }
     free(wt); free(has); free(scratch);
+    return rc;
+}
+
+int orc_refine_search(int32_t k, const uint64_t *W, int32_t anchor, int32_t mode,
+                      const int32_t *load, const int32_t *cap, const int32_t *pen,
+                      int64_t *dist, int32_t *pred, int32_t *rounds) {
+    if (k < 1 || !pen) return ORC_E_INVAL;
+    int64_t *off = (int64_t *)malloc(sizeof(int64_t) * ((size_t)k + 1));
+    if (!off) return ORC_E_NOMEM;
+    pen_table P;
+    flat_table(k, pen, off, &P);
+    int rc = orc_refine_search_q(k, W, anchor, mode, load, cap, off, pen, dist, pred, rounds);
+    free(off);
     return rc;
 }
 
@@ -305,7 +373,8 @@ static void heap_pop(heap_t *h) {
 typedef struct {
     int32_t k;
     int64_t n;
-    const int32_t *cm, *cap, *pen;
+    const int32_t *cm, *cap;
+    pen_table P;            /* penalty function of every center */
     int32_t *smin, *mc, *a, *load;
     int64_t *order, *rank;
     heap_t *H;              /* k*k heaps; H[u*k+v] */
@@ -363,7 +432,7 @@ static int refine(orc_state *S, int32_t s, int mode, int64_t *applied, int64_t *
     const int32_t k = S->k, K1 = k + 1;
     *applied = 0; *edges = 0;
     refresh_W(S);
-    build_split_graph(k, S->W, s, mode, S->load, S->cap, S->pen, S->wt, S->has);
+    build_split_graph(k, S->W, s, mode, S->load, S->cap, &S->P, S->wt, S->has);
     int rc = bellman_ford(K1, s, S->wt, S->has, S->dist, S->pred, S->scratch, rounds);
     S->stats[5] += *rounds;
     if (rc) return rc;
@@ -418,19 +487,18 @@ static void state_free(orc_state *S) {
     free(S->W); free(S->wt); free(S->dist); free(S->scratch); free(S->has); free(S->pred);
 }
 
-/* ASRAL (Algorithm 2).  Runs iterations 0 .. min(n, max_iters)-1.
- * Outputs: assign[n] (center per unit id, -1 if not yet allotted), load[k],
- * objective, optionally W (k*k, the heap tops after the last iteration),
- * trace (ORC_TRACE_W int64 per iteration) and stats (ORC_STATS_N int64).     */
-int orc_solve(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap,
-              const int32_t *pen, int64_t max_iters, int32_t *assign, int32_t *load_out,
-              int64_t *objective, uint64_t *W_out, int64_t *trace, int64_t *stats) {
-    int rc = validate(k, n, cm, cap, pen);
-    if (rc) return rc;
-    if (!cap || !pen || !assign || !objective) return ORC_E_INVAL;
+/* ASRAL (Algorithm 2) with the penalty function P, on validated inputs.
+ * Runs iterations 0 .. min(n, max_iters)-1.  Outputs: assign[n] (center per
+ * unit id, -1 if not yet allotted), load[k], objective, optionally W (k*k,
+ * the heap tops after the last iteration), trace (ORC_TRACE_W int64 per
+ * iteration) and stats (ORC_STATS_N int64).                                  */
+static int solve_core(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap,
+                      const pen_table *P, int64_t max_iters, int32_t *assign, int32_t *load_out,
+                      int64_t *objective, uint64_t *W_out, int64_t *trace, int64_t *stats) {
+    int rc = ORC_OK;
     orc_state S;
     memset(&S, 0, sizeof(S));
-    S.k = k; S.n = n; S.cm = cm; S.cap = cap; S.pen = pen;
+    S.k = k; S.n = n; S.cm = cm; S.cap = cap; S.P = *P;
     const int32_t K1 = k + 1;
     S.smin = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     S.mc = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
@@ -460,9 +528,11 @@ int orc_solve(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap,
         int64_t d = S.order[r];              /* extract-min on MinDistance */
         int32_t s = S.smin[d];
         int vacant = S.load[s] < cap[s];
+        /* Case (b): the unit is the (load - cap + 1)-th beyond capacity */
+        int64_t q = q_next(&S.P, S.load, cap, s);
         S.a[d] = s;
         S.load[s] += 1;
-        delta += (int64_t)cm[d * (int64_t)k + s] + (vacant ? 0 : pen[s]);
+        delta += (int64_t)cm[d * (int64_t)k + s] + q;
         rc = heaps_insert_unit(&S, d, s);
         if (rc) break;
 
@@ -494,6 +564,35 @@ int orc_solve(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap,
     }
     state_free(&S);
     return rc;
+}
+
+/* ASRAL with one constant per-unit penalty per center, pen[k].               */
+int orc_solve(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap,
+              const int32_t *pen, int64_t max_iters, int32_t *assign, int32_t *load_out,
+              int64_t *objective, uint64_t *W_out, int64_t *trace, int64_t *stats) {
+    int rc = validate(k, n, cm, cap, pen);
+    if (rc) return rc;
+    if (!cap || !pen || !assign || !objective) return ORC_E_INVAL;
+    int64_t *off = (int64_t *)malloc(sizeof(int64_t) * ((size_t)k + 1));
+    if (!off) return ORC_E_NOMEM;
+    pen_table P;
+    flat_table(k, pen, off, &P);
+    rc = solve_core(k, n, cm, cap, &P, max_iters, assign, load_out, objective, W_out, trace, stats);
+    free(off);
+    return rc;
+}
+
+/* ASRAL with a penalty table per center: the j-th unit beyond the capacity
+ * of s pays pen_val[pen_off[s] + min(j, len_s) - 1] (see pen_table).         */
+int orc_solve_q(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap,
+                const int64_t *pen_off, const int32_t *pen_val, int64_t max_iters,
+                int32_t *assign, int32_t *load_out, int64_t *objective, uint64_t *W_out,
+                int64_t *trace, int64_t *stats) {
+    int rc = validate(k, n, cm, cap, NULL);
+    if (rc) return rc;
+    if (!cap || !assign || !objective || validate_table(k, pen_off, pen_val)) return ORC_E_INVAL;
+    const pen_table P = {pen_off, pen_val};
+    return solve_core(k, n, cm, cap, &P, max_iters, assign, load_out, objective, W_out, trace, stats);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -543,7 +642,10 @@ int orc_solve_strict(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap
 
     orc_state S;
     memset(&S, 0, sizeof(S));
-    S.k = kx; S.n = n; S.cm = cmx; S.cap = capx; S.pen = pen1; S.strict = 1;
+    int64_t *off1 = (int64_t *)malloc(sizeof(int64_t) * ((size_t)kx + 1));
+    if (!off1) { free(cmx); free(capx); free(pen1); return ORC_E_NOMEM; }
+    S.k = kx; S.n = n; S.cm = cmx; S.cap = capx; S.strict = 1;
+    flat_table(kx, pen1, off1, &S.P);
     const int32_t K1 = kx + 1;
     S.smin = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     S.mc = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
@@ -601,6 +703,6 @@ int orc_solve_strict(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap
         if (stats) memcpy(stats, S.stats, sizeof(S.stats));
     }
     state_free(&S);
-    free(cmx); free(capx); free(pen1);
+    free(cmx); free(capx); free(pen1); free(off1);
     return rc;
 }

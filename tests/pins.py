@@ -24,6 +24,44 @@ def eq1(cm, cap, pen, assign) -> int:
     return total + int((over * np.asarray(pen, np.int64)).sum())
 
 
+def table_penalty(off, val, s: int, j: int) -> int:
+    """Penalty of the j-th unit (j >= 1) beyond the capacity of center s: the
+    j-th value of the center's table, its last value for every later unit."""
+    lo, hi = int(off[s]), int(off[s + 1])
+    return int(val[lo + min(j, hi - lo) - 1])
+
+
+def eq2(cm, cap, off, val, assign) -> int:
+    """Equation (2): the sum of CM over the allotment plus, for every center,
+    the penalties of its 1st .. (load - capacity)-th units beyond capacity."""
+    cm = np.asarray(cm, np.int64)
+    a = np.asarray(assign)
+    ok = a >= 0
+    total = int(cm[np.nonzero(ok)[0], a[ok]].sum())
+    load = np.bincount(a[ok], minlength=cm.shape[1])
+    for s in range(cm.shape[1]):
+        for j in range(1, int(load[s]) - int(cap[s]) + 1):
+            total += table_penalty(off, val, s, j)
+    return total
+
+
+def opt_convex(cm, cap, off, val) -> int:
+    """Exact optimum of Equation (2) for non-decreasing penalties: center s
+    offers cap[s] slots at CM(d,s) and then, for j = 1..n, a slot at CM(d,s)
+    plus the j-th overload penalty.  The penalties do not decrease, so an
+    optimal matching fills each center's slots in order and its cost is the
+    objective; scipy's assignment solver finds it."""
+    cm = np.asarray(cm, np.int64)
+    n, k = cm.shape
+    cols = []
+    for s in range(k):
+        cols += [cm[:, s]] * int(min(cap[s], n))
+        cols += [cm[:, s] + table_penalty(off, val, s, j) for j in range(1, n + 1)]
+    cost = np.stack(cols, axis=1)
+    r, c = linear_sum_assignment(cost)
+    return int(cost[r, c].sum())
+
+
 def opt_brute(cm, cap, pen) -> int:
     """Exact optimum of Equation (1) by enumerating all k^n complete allotments."""
     cm = np.asarray(cm, np.int64)

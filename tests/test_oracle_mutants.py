@@ -20,8 +20,15 @@ from tests.test_oracle_pins import _load, _random_W
 
 MUTANTS = {
     "transfer_cost_sign": ("(int64_t)row[v] - row[u], S->rank[d]", "(int64_t)row[u] - row[v], S->rank[d]"),
-    "no_penalty_on_overload": ("(vacant ? 0 : pen[s])", "0"),
-    "penalty_edge_ignores_load": ("(load[u] >= cap[u]) ? pen[u] : 0", "pen[u]"),
+    "no_penalty_on_overload": ("delta += (int64_t)cm[d * (int64_t)k + s] + q;",
+                               "delta += (int64_t)cm[d * (int64_t)k + s];"),
+    "penalty_edge_ignores_load": ("wt[(int64_t)u * K1 + k] = q_next(P, load, cap, u) - q_last(P, load, cap, anchor);",
+                                  "wt[(int64_t)u * K1 + k] = q_at(P, u, 1) - q_last(P, load, cap, anchor);"),
+    "q_next_first_value_only": ("return load[u] >= cap[u] ? q_at(P, u, (int64_t)load[u] - cap[u] + 1) : 0;",
+                                "return load[u] >= cap[u] ? q_at(P, u, 1) : 0;"),
+    "q_last_off_by_one": ("q_at(P, u, load[u] > cap[u] ? (int64_t)load[u] - cap[u] : 1);",
+                          "q_at(P, u, load[u] > cap[u] ? (int64_t)load[u] - cap[u] + 1 : 1);"),
+    "q_table_tail_uses_first_value": ("(j < len ? j : len) - 1]", "(j < len ? j : 1) - 1]"),
     "vacancy_off_by_one": ("int vacant = S.load[s] < cap[s];", "int vacant = S.load[s] <= cap[s];"),
     "no_path_refinement": ("if (!vacant) {", "if (0) {"),
     "no_cycle_refinement": ("rc = refine(&S, s, 0, &cyc_cost", "if (0) rc = refine(&S, s, 0, &cyc_cost"),
@@ -111,8 +118,20 @@ def _pin_failures(lib):
                 return False
         return True
 
+    def table_ok():
+        from tests.test_oracle_penalty import random_table
+        for s in range(8):
+            inst = L.random_small(k=2 + s % 4, n=30, seed=70 + s, cm_hi=40, cap="tight")
+            off, val = random_table(np.random.default_rng(s), inst.k, 12)
+            for r in (10, 30):
+                st = oracle.solve_q(inst.cm, inst.cap, off, val, max_iters=r, want_trace=True, lib=lib)
+                if st.objective != pins.eq2(inst.cm, inst.cap, off, val, st.assign):
+                    return False
+        return True
+
     for name, fn in [("setup", setup_ok), ("hand_trace", hand_trace_ok), ("search", search_ok),
-                     ("solve", solve_ok), ("zero_cap", zero_cap_ok), ("strict", strict_ok)]:
+                     ("solve", solve_ok), ("zero_cap", zero_cap_ok), ("strict", strict_ok),
+                     ("table", table_ok)]:
         check(name, fn)
     return fails
 
