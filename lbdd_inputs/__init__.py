@@ -27,7 +27,9 @@ with the same numpy.  Distances use only IEEE add, multiply, abs and sqrt
 
 Penalties are one constant per center, as in the paper's experiments (Section
 5, "For sake of easy interpretation ... each service center has a penalty
-value (chosen randomly) inside a range").
+value (chosen randomly) inside a range").  ``rising_penalties`` turns them into
+the general increasing penalty functions of the problem statement (Section 2),
+as one table per center.
 """
 from __future__ import annotations
 
@@ -39,7 +41,8 @@ import numpy as np
 __all__ = [
     "Instance", "make_config", "uniform_euclid", "gmm_manhattan",
     "random_small", "batch_specs", "make_batch_instance", "serving_trace",
-    "input_hash", "CONFIG_NAMES",
+    "input_hash", "CONFIG_NAMES", "rising_penalties", "RoadNetwork", "road_network",
+    "make_road_config", "ROAD_CONFIG_NAMES",
 ]
 
 CONFIG_NAMES = ("C1", "C2", "C3")
@@ -191,6 +194,109 @@ def random_small(k: int, n: int, seed: int, cm_hi: int = 100, cap: str | int = "
     return Instance(f"random_small(k={k},n={n},seed={seed},cap={cap},cm_hi={cm_hi})",
                     k, n, np.ascontiguousarray(cm), capv.astype(np.int32), pen,
                     dict(generator="random_small", seed=seed))
+
+
+def rising_penalties(inst: Instance, length: int, seed: int, step_hi: int = 20):
+    """Penalty tables (offsets[k+1] int64, values int32) that start at the
+    instance's constant penalty and rise by U{0..step_hi} per further unit
+    beyond capacity, ``length`` values per center (the last one holds for
+    every later unit)."""
+    g = _rng(8_000_000 + seed, inst.k, length)
+    steps = g.integers(0, step_hi + 1, size=(inst.k, length), dtype=np.int64)
+    steps[:, 0] = 0
+    vals = np.asarray(inst.pen, np.int64)[:, None] + np.cumsum(steps, axis=1)
+    off = np.arange(inst.k + 1, dtype=np.int64) * length
+    return off, np.ascontiguousarray(vals.reshape(-1)).astype(np.int32)
+
+
+@dataclass
+class RoadNetwork:
+    """A road-like network with centers and demand units on its vertices: the
+    input of the cost-matrix construction (CM(d, s) = shortest-path length
+    from the vertex of center s to the vertex of unit d).  CSR arcs: arcs
+    row_ptr[u] .. row_ptr[u+1]-1 leave u; every road is two arcs."""
+    name: str
+    V: int
+    row_ptr: np.ndarray           # int64 (V + 1,)
+    col: np.ndarray               # int32 (E,)
+    length: np.ndarray            # int32 (E,)
+    centers: np.ndarray           # int32 (k,) vertex of each center
+    units: np.ndarray             # int32 (n,) vertex of each unit
+    cap: np.ndarray               # int32 (k,)
+    pen: np.ndarray               # int32 (k,)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def k(self) -> int:
+        return len(self.centers)
+
+    @property
+    def n(self) -> int:
+        return len(self.units)
+
+
+def road_network(V: int, width: int, k: int, seed: int, theta: float = 0.7, pen_lo: int = 1,
+                 pen_hi: int = 200, keep_vertical: float = 0.7, diagonal: float = 0.05,
+                 name: str = "") -> RoadNetwork:
+    """Stand-in for a city road network (the paper's is OpenStreetMap data
+    that is not available): vertices on a jittered grid of ``width`` columns
+    (the last row may be partial), 100 length units apart.  Every horizontal
+    street segment exists; vertical ones with probability ``keep_vertical``
+    (always in column 0, so the network is connected); diagonal shortcuts
+    with probability ``diagonal`` at 0.8 of their Euclidean length (faster
+    roads).  Lengths are rounded half-up.  As in the paper's setup, ``k``
+    random vertices are centers and every other vertex holds one demand unit;
+    total capacity floor(theta * n) is split at random, penalties are
+    U{pen_lo..pen_hi} per center."""
+    g = _rng(9_000_000 + seed, V, width)
+    idx = np.arange(V, dtype=np.int64)
+    row, colm = idx // width, idx % width
+    x = colm * 100.0 + g.uniform(-30.0, 30.0, size=V)
+    y = row * 100.0 + g.uniform(-30.0, 30.0, size=V)
+    src, dst, fac = [], [], []
+    h = idx[(colm + 1 < width) & (idx + 1 < V)]
+    src.append(h); dst.append(h + 1); fac.append(np.ones(len(h)))
+    vcand = idx[idx + width < V]
+    vkeep = vcand[(g.random(len(vcand)) < keep_vertical) | (colm[vcand] == 0)]
+    src.append(vkeep); dst.append(vkeep + width); fac.append(np.ones(len(vkeep)))
+    dcand = idx[(colm + 1 < width) & (idx + width + 1 < V)]
+    dkeep = dcand[g.random(len(dcand)) < diagonal]
+    src.append(dkeep); dst.append(dkeep + width + 1); fac.append(np.full(len(dkeep), 0.8))
+    a = np.concatenate(src); b = np.concatenate(dst); f = np.concatenate(fac)
+    dx, dy = x[a] - x[b], y[a] - y[b]
+    ln = _round_half_up(f * np.sqrt(dx * dx + dy * dy)).astype(np.int64)
+    u = np.concatenate([a, b]); v = np.concatenate([b, a]); w = np.concatenate([ln, ln])
+    order = np.lexsort((v, u))
+    u, v, w = u[order], v[order], w[order]
+    row_ptr = np.zeros(V + 1, np.int64)
+    np.add.at(row_ptr, u + 1, 1)
+    row_ptr = np.cumsum(row_ptr)
+    gc = _rng(9_100_000 + seed, V, k)
+    centers = np.sort(gc.choice(V, size=k, replace=False)).astype(np.int32)
+    mask = np.ones(V, bool)
+    mask[centers] = False
+    units = np.nonzero(mask)[0].astype(np.int32)
+    n = len(units)
+    cap = _apportion(int(np.floor(theta * n)), gc.uniform(0.2, 1.0, size=k))
+    pen = gc.integers(pen_lo, pen_hi + 1, size=k, dtype=np.int64).astype(np.int32)
+    return RoadNetwork(name or f"road_network(V={V},width={width},k={k},seed={seed})", V,
+                       row_ptr, v.astype(np.int32), w.astype(np.int32), centers, units, cap, pen,
+                       dict(generator="road_network", seed=seed, theta=theta, width=width))
+
+
+ROAD_CONFIG_NAMES = ("R1", "R2")
+
+
+def make_road_config(name: str) -> RoadNetwork:
+    """Workloads shaped like the paper's experiments (Section 5): a 65,902-vertex
+    network, service center ratio 500:1 (k=131, n=65,771) with high total
+    capacity (theta 0.7) and penalties U{1..200}; and ratio 900:1 (k=73,
+    n=65,829) with low capacity (theta 0.3) and penalties U{200..400}."""
+    if name == "R1":
+        return road_network(65_902, 257, 131, seed=1, theta=0.7, pen_lo=1, pen_hi=200, name="R1")
+    if name == "R2":
+        return road_network(65_902, 257, 73, seed=2, theta=0.3, pen_lo=200, pen_hi=400, name="R2")
+    raise KeyError(name)
 
 
 def batch_specs(count: int = 256, seed: int = 4):

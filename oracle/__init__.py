@@ -56,9 +56,10 @@ def _load(path: str = LIB):
     lib.orc_solve_strict.argtypes = [C.c_int32, C.c_int64, P, P, C.c_int64, P, P, P, P, P, P]
     lib.orc_solve_q.argtypes = [C.c_int32, C.c_int64, P, P, P, P, C.c_int64, P, P, P, P, P, P]
     lib.orc_refine_search_q.argtypes = [C.c_int32, P, C.c_int32, C.c_int32, P, P, P, P, P, P, P]
+    lib.orc_road_cm.argtypes = [C.c_int32, P, P, P, C.c_int32, P, C.c_int64, P, P]
     for f in (lib.orc_setup, lib.orc_best_transfers, lib.orc_objective,
               lib.orc_refine_search, lib.orc_solve, lib.orc_solve_strict, lib.orc_solve_q,
-              lib.orc_refine_search_q):
+              lib.orc_refine_search_q, lib.orc_road_cm):
         f.restype = C.c_int
     if path == LIB:
         _lib = lib
@@ -241,3 +242,20 @@ def solve_q(cm, cap, pen_off, pen_val, max_iters: int = -1, want_W: bool = False
     if rc:
         raise OracleError(rc, "orc_solve_q")
     return Result(assign, load, int(obj[0]), W, trace[:iters] if trace is not None else None, stats)
+
+
+def road_cm(row_ptr, col, length, centers, units, lib=None) -> np.ndarray:
+    """Cost matrix [n][k] int32 from a road network: the shortest-path length
+    from the vertex of each center to the vertex of each unit (Dijkstra from
+    every center).  The graph is CSR: arcs row_ptr[u]..row_ptr[u+1]-1 leave u."""
+    lib = lib or _load()
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    V = len(rp) - 1
+    centers = _i32(centers); units = _i32(units)
+    k, n = len(centers), len(units)
+    cm = np.empty((n, k), np.int32)
+    rc = lib.orc_road_cm(V, _p(rp), _p(_i32(col)), _p(_i32(length)), k, _p(centers), n,
+                         _p(units), _p(cm))
+    if rc:
+        raise OracleError(rc, "orc_road_cm")
+    return cm

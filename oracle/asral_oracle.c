@@ -26,6 +26,9 @@
  *                        center (Definition of the penalty function, Section
  *                        2), given as a table of the penalties of successive
  *                        units beyond capacity.
+ *   orc_road_cm          the cost matrix from a road network: shortest-path
+ *                        lengths from every center (Section 3.5, construction
+ *                        of CM), by Dijkstra.
  *   orc_objective        the objective of Equation (1) with one constant
  *                        per-unit penalty per center.
  *
@@ -704,5 +707,92 @@ int orc_solve_strict(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap
     }
     state_free(&S);
     free(cmx); free(capx); free(pen1); free(off1);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cost matrix from a road network (construction of CM, Section 3.5; Datasets,
+ * Section 5): CM(d, s) is the length of a shortest path from the vertex of
+ * center s to the vertex of unit d.  Dijkstra from every center with a binary
+ * min-heap of (distance, vertex) pairs and lazy deletion (a popped pair whose
+ * distance is above the vertex's label is stale and skipped).
+ *   graph     CSR over V vertices: arcs row_ptr[u] .. row_ptr[u+1]-1 leave u,
+ *             arc i goes to col[i] with length len[i] >= 0 (a two-way road is
+ *             two arcs)
+ *   centers   [k] vertex of each center; units [n] vertex of each unit
+ *   cm        [n][k] output
+ * Fails with ORC_E_INVAL on bad indices or lengths, and when some unit's
+ * vertex cannot be reached from some center or lies 2^30 or more away.      */
+typedef struct { int64_t d; int32_t v; } dv_pair;
+
+static int dv_less(dv_pair a, dv_pair b) { return a.d < b.d || (a.d == b.d && a.v < b.v); }
+
+static void dv_push(dv_pair *h, int64_t *size, dv_pair x) {
+    int64_t i = (*size)++;
+    h[i] = x;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (!dv_less(h[i], h[p])) break;
+        dv_pair t = h[p]; h[p] = h[i]; h[i] = t;
+        i = p;
+    }
+}
+
+static dv_pair dv_pop(dv_pair *h, int64_t *size) {
+    dv_pair top = h[0];
+    h[0] = h[--(*size)];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, m = i;
+        if (l < *size && dv_less(h[l], h[m])) m = l;
+        if (r < *size && dv_less(h[r], h[m])) m = r;
+        if (m == i) break;
+        dv_pair t = h[m]; h[m] = h[i]; h[i] = t;
+        i = m;
+    }
+    return top;
+}
+
+int orc_road_cm(int32_t V, const int64_t *row_ptr, const int32_t *col, const int32_t *len,
+                int32_t k, const int32_t *centers, int64_t n, const int32_t *units, int32_t *cm) {
+    if (V < 1 || k < 1 || n < 1 || !row_ptr || !col || !len || !centers || !units || !cm)
+        return ORC_E_INVAL;
+    if (row_ptr[0] != 0) return ORC_E_INVAL;
+    for (int32_t u = 0; u < V; ++u)
+        if (row_ptr[u + 1] < row_ptr[u]) return ORC_E_INVAL;
+    const int64_t E = row_ptr[V];
+    for (int64_t i = 0; i < E; ++i)
+        if (col[i] < 0 || col[i] >= V || len[i] < 0 || len[i] >= CM_LIMIT) return ORC_E_INVAL;
+    for (int32_t s = 0; s < k; ++s) if (centers[s] < 0 || centers[s] >= V) return ORC_E_INVAL;
+    for (int64_t d = 0; d < n; ++d) if (units[d] < 0 || units[d] >= V) return ORC_E_INVAL;
+    int64_t *dist = (int64_t *)malloc(sizeof(int64_t) * (size_t)V);
+    dv_pair *heap = (dv_pair *)malloc(sizeof(dv_pair) * (size_t)(E + 1));
+    if (!dist || !heap) { free(dist); free(heap); return ORC_E_NOMEM; }
+    int rc = ORC_OK;
+    for (int32_t s = 0; s < k && !rc; ++s) {
+        for (int32_t v = 0; v < V; ++v) dist[v] = DIST_NONE;
+        int64_t size = 0;
+        dist[centers[s]] = 0;
+        dv_pair start = {0, centers[s]};
+        dv_push(heap, &size, start);
+        while (size > 0) {
+            dv_pair x = dv_pop(heap, &size);
+            if (x.d > dist[x.v]) continue;            /* stale entry */
+            for (int64_t i = row_ptr[x.v]; i < row_ptr[x.v + 1]; ++i) {
+                int64_t c = x.d + len[i];
+                if (c < dist[col[i]]) {
+                    dist[col[i]] = c;
+                    dv_pair y = {c, col[i]};
+                    dv_push(heap, &size, y);          /* at most one push per arc */
+                }
+            }
+        }
+        for (int64_t d = 0; d < n; ++d) {
+            int64_t c = dist[units[d]];
+            if (c == DIST_NONE || c >= CM_LIMIT) { rc = ORC_E_INVAL; break; }
+            cm[d * (int64_t)k + s] = (int32_t)c;
+        }
+    }
+    free(dist); free(heap);
     return rc;
 }

@@ -29,6 +29,10 @@ MUTANTS = {
     "q_last_off_by_one": ("q_at(P, u, load[u] > cap[u] ? (int64_t)load[u] - cap[u] : 1);",
                           "q_at(P, u, load[u] > cap[u] ? (int64_t)load[u] - cap[u] + 1 : 1);"),
     "q_table_tail_uses_first_value": ("(j < len ? j : len) - 1]", "(j < len ? j : 1) - 1]"),
+    "road_skips_last_arc": ("for (int64_t i = row_ptr[x.v]; i < row_ptr[x.v + 1]; ++i) {",
+                            "for (int64_t i = row_ptr[x.v]; i + 1 < row_ptr[x.v + 1]; ++i) {"),
+    "road_settled_entries_skipped": ("if (x.d > dist[x.v]) continue;",
+                                     "if (x.d >= dist[x.v] && x.d > 0) continue;"),
     "vacancy_off_by_one": ("int vacant = S.load[s] < cap[s];", "int vacant = S.load[s] <= cap[s];"),
     "no_path_refinement": ("if (!vacant) {", "if (0) {"),
     "no_cycle_refinement": ("rc = refine(&S, s, 0, &cyc_cost", "if (0) rc = refine(&S, s, 0, &cyc_cost"),
@@ -129,9 +133,20 @@ def _pin_failures(lib):
                     return False
         return True
 
+    def road_ok():
+        from scipy.sparse import csr_matrix
+        from scipy.sparse.csgraph import dijkstra
+        for s in range(3):
+            net = L.road_network(600 + 11 * s, 25, 6, seed=s)
+            cm = oracle.road_cm(net.row_ptr, net.col, net.length, net.centers, net.units, lib=lib)
+            G = csr_matrix((net.length.astype(np.float64), net.col, net.row_ptr), shape=(net.V, net.V))
+            if not np.array_equal(cm, dijkstra(G, indices=net.centers)[:, net.units].T.astype(np.int64)):
+                return False
+        return True
+
     for name, fn in [("setup", setup_ok), ("hand_trace", hand_trace_ok), ("search", search_ok),
                      ("solve", solve_ok), ("zero_cap", zero_cap_ok), ("strict", strict_ok),
-                     ("table", table_ok)]:
+                     ("table", table_ok), ("road", road_ok)]:
         check(name, fn)
     return fails
 
