@@ -202,6 +202,8 @@ def main():
                     help="requests of a Poisson trace to serve vs plain FIFO (0: skip)")
     ap.add_argument("--serve-max-n", type=int, default=200_000)
     ap.add_argument("--serve-max-k", type=int, default=256)
+    ap.add_argument("--no-road", action="store_true",
+                    help="skip the road-network workload (cost matrix on the GPU, then a solve)")
     ap.add_argument("--no-strict", action="store_true",
                     help="skip the strict-LBDD (Appendix B) solve of the same instance")
     ap.add_argument("--cpu-batch", action="store_true",
@@ -385,6 +387,56 @@ def main():
                   "stats": sst}
         log(f"bench: strict solve {smean:.1f} ms, parity {strict['objective_matches_oracle']}")
 
+    road = None
+    if not args.no_road:
+        log("bench: road-network workload R1 (65,902 vertices, k=131, n=65,771)")
+        net = L.make_road_config("R1")
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(dev)
+        g_rp, g_col, g_len = t(net.row_ptr, np.int64), t(net.col, np.int32), t(net.length, np.int32)
+        g_cen, g_units = t(net.centers, np.int32), t(net.units, np.int32)
+        rwork = torch.empty(lbdd.load().lbdd_road_cm_work_bytes(net.V, net.k), dtype=torch.uint8,
+                            device=dev)
+        rcm = lbdd.road_cost_matrix(g_rp, g_col, g_len, g_cen, g_units, work=rwork, stream=stream)
+        torch.cuda.synchronize()
+        reps = 5
+        tc = time.perf_counter()
+        for _ in range(reps):
+            rcm = lbdd.road_cost_matrix(g_rp, g_col, g_len, g_cen, g_units, work=rwork, stream=stream)
+        torch.cuda.synchronize()
+        cm_ms = (time.perf_counter() - tc) * 1e3 / reps
+        h = lbdd.Instance(rcm, net.cap, net.pen, stream=stream)
+        ev0.record(stream)
+        h.solve()
+        ev1.record(stream)
+        robj = h.objective()
+        rsolve_ms = ev0.elapsed_time(ev1)
+        rst = h.stats()
+        h.close()
+        road = {"workload": "R1: road-like network of 65,902 vertices (jittered grid, 257 wide), "
+                            "131 centers, one demand unit on each other vertex (service center "
+                            "ratio 500:1), total capacity 0.7n, penalties U{1..200}",
+                "cost_matrix_ms": round(cm_ms, 3), "arcs": int(len(net.col)),
+                "solve_ms": round(rsolve_ms, 3), "objective": robj,
+                "cycles": rst["cycles"], "paths": rst["paths"]}
+        log(f"bench: road CM {cm_ms:.2f} ms, solve {rsolve_ms:.1f} ms")
+        if not args.no_cpu_baseline:
+            import oracle
+            tc = time.perf_counter()
+            cm_ref = oracle.road_cm(net.row_ptr, net.col, net.length, net.centers, net.units)
+            t_cm = time.perf_counter() - tc
+            tc = time.perf_counter()
+            r_ref = oracle.solve(cm_ref, net.cap, net.pen)
+            t_solve = time.perf_counter() - tc
+            road["cost_matrix_matches_oracle"] = bool(np.array_equal(rcm.cpu().numpy(), cm_ref))
+            road["objective_matches_oracle"] = r_ref.objective == robj
+            road["cpu_baseline"] = {
+                "value": round(1.0 / (t_cm + t_solve), 5), "unit": "workloads/s", "cores": 1,
+                "kind": "oracle",
+                "sample": f"the same workload once: Dijkstra from every center {t_cm:.2f} s, "
+                          f"ASRAL solve {t_solve:.1f} s"}
+            log(f"bench: road oracle: cost matrix {t_cm:.2f} s, solve {t_solve:.1f} s")
+        del g_rp, g_col, g_len, g_cen, g_units, rwork, rcm
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -426,6 +478,7 @@ def main():
         "batch": batch,
         "serve": serve,
         "strict": strict,
+        "road": road,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -85,6 +85,50 @@ int lbdd_create(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity
                 const int32_t *penalty, uint32_t flags, void *hip_stream,
                 lbdd_instance **out);
 
+/* Create an instance whose penalty is a general function of the overload
+ * (Definition of the penalty function, Section 2: the j-th unit beyond the
+ * capacity of s pays q_s(j) > 0, non-decreasing in j), given as one table
+ * per center: q_s(j) = pen_val[pen_off[s] + min(j, len_s) - 1] with
+ * len_s = pen_off[s + 1] - pen_off[s] >= 1, so a table's last value holds for
+ * every later unit (a table of one value is the constant penalty of
+ * lbdd_create).  The objective is then Equation (2): CM over the allotment
+ * plus, for every center, q_s(1) + ... + q_s(load - capacity).  The
+ * allotment to a full center adds q_s(load - capacity + 1); the path search's
+ * edge u -> s*_in costs what one more unit at u would pay minus what the
+ * anchor's last unit beyond capacity pays.
+ *   k, n, cm, capacity, flags, hip_stream, out   as lbdd_create
+ *   pen_off     [k + 1] int64 host array, pen_off[0] = 0, strictly increasing
+ *   pen_val     [pen_off[k]] int32 host array, values in [1, 2^30),
+ *               non-decreasing within each center; both copied
+ * Errors: as lbdd_create, and LBDD_E_INVAL for a malformed table. */
+int lbdd_create_penalty_table(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity,
+                              const int64_t *pen_off, const int32_t *pen_val, uint32_t flags,
+                              void *hip_stream, lbdd_instance **out);
+
+/* Cost matrix from a road network (construction of CM, Section 3.5; the
+ * paper's datasets, Section 5): CM(d, s) = length of a shortest path from
+ * the vertex of center s to the vertex of unit d.  All arrays are device
+ * pointers:
+ *   V           vertices (>= 1)
+ *   row_ptr     [V + 1] int64 CSR offsets: the arcs leaving u are
+ *               row_ptr[u] .. row_ptr[u + 1] - 1 (row_ptr[0] = 0)
+ *   col, length [row_ptr[V]] int32 head vertex and length (in [0, 2^30)) of
+ *               every arc; a two-way road is two arcs
+ *   centers     [k] int32 vertex of every center (1 <= k <= LBDD_MAX_K)
+ *   units       [n] int32 vertex of every demand unit
+ *   cm          [n][k] int32 output, ready for lbdd_create(LBDD_CM_DEVICE)
+ *   work        lbdd_road_cm_work_bytes(V, k) bytes of device scratch
+ *               (owned by the caller, 16 bytes per vertex per center, for at
+ *               most 256 centers at a time)
+ * The input is checked on the device before the searches run; the call
+ * synchronises with the stream.  Errors: LBDD_E_INVAL (sizes, NULL, a
+ * malformed network, or a unit unreachable from a center or 2^30 or more
+ * away), LBDD_E_DEVICE. */
+size_t lbdd_road_cm_work_bytes(int32_t V, int32_t k);
+int lbdd_road_cost_matrix(int32_t V, const int64_t *row_ptr, const int32_t *col, const int32_t *length,
+                          int32_t k, const int32_t *centers, int64_t n, const int32_t *units, int32_t *cm,
+                          void *work, void *hip_stream);
+
 /* Create a strict-LBDD instance (Appendix B): no center may take more units
  * than its capacity and the objective is Equation (3), the sum of CM over the
  * allotment.  Solved by Algorithm 4, which Theorem 2 makes exact: each unit

@@ -18,6 +18,7 @@
 #include "../../include/lbdd.h"
 #include "instance.hpp"
 #include "lbdd_dev.hpp"
+#include "road.hpp"
 
 namespace {
 
@@ -56,7 +57,8 @@ void release(lbdd_instance *h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->st);
   void *ptrs[] = {h->cm, h->smin, h->cap, h->pen, h->assign, h->load, h->members,
-                  h->slot, h->unperm, h->order, h->scalars, h->W, h->Wh, h->best, h->meta, h->thr};
+                  h->slot, h->unperm, h->order, h->scalars, h->W, h->Wh, h->best, h->meta, h->thr,
+                  h->poff, h->pval};
   for (void *p : ptrs)
     if (p) (void)hipFreeAsync(p, h->st);
   (void)hipStreamSynchronize(h->st);
@@ -103,19 +105,38 @@ const char *lbdd_last_error(void) { return g_err.c_str(); }
 
 namespace {
 
-// lbdd_create and lbdd_create_strict.  A strict instance with excess demand
-// gets the dummy center as its center k (capacity n - sum, cost largest
-// entry + 1); its penalties are unused.
+// lbdd_create, lbdd_create_strict and lbdd_create_penalty_table.  A strict
+// instance with excess demand gets the dummy center as its center k
+// (capacity n - sum, cost largest entry + 1); its penalties are unused.  With
+// penalty tables (pen_off, pen_val) `penalty` is NULL.
 int create_instance(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity,
-                    const int32_t *penalty, uint32_t flags, void *hip_stream, bool strict,
-                    lbdd_instance **out) {
+                    const int32_t *penalty, const int64_t *pen_off, const int32_t *pen_val,
+                    uint32_t flags, void *hip_stream, bool strict, lbdd_instance **out) {
   g_err.clear();
   if (!out) return fail(LBDD_E_INVAL, "out is NULL");
   *out = nullptr;
   if (k < 1 || k > LBDD_MAX_K) return fail(LBDD_E_INVAL, "k=%d outside [1, %d]", k, LBDD_MAX_K);
   if (n < 1 || n > LBDD_MAX_N) return fail(LBDD_E_INVAL, "n=%lld outside [1, 2^31-1]", (long long)n);
-  if (!cm || !capacity || (!penalty && !strict)) return fail(LBDD_E_INVAL, "NULL input array");
+  const bool table = pen_off != nullptr || pen_val != nullptr;
+  if (!cm || !capacity || (!penalty && !strict && !table) || (table && (!pen_off || !pen_val)))
+    return fail(LBDD_E_INVAL, "NULL input array");
   if (flags & ~LBDD_CM_DEVICE) return fail(LBDD_E_INVAL, "unknown flags 0x%x", flags);
+  std::vector<int32_t> first;                     // a table's first values stand in for pen[]
+  if (table) {
+    if (pen_off[0] != 0) return fail(LBDD_E_INVAL, "pen_off[0]=%lld, expected 0", (long long)pen_off[0]);
+    for (int32_t s = 0; s < k; ++s) {
+      if (pen_off[s + 1] <= pen_off[s])
+        return fail(LBDD_E_INVAL, "center %d has no penalty values (pen_off not increasing)", s);
+      for (int64_t i = pen_off[s]; i < pen_off[s + 1]; ++i) {
+        if (pen_val[i] < 1 || pen_val[i] >= lbdd::CM_LIMIT)
+          return fail(LBDD_E_INVAL, "pen_val[%lld]=%d outside [1, 2^30)", (long long)i, pen_val[i]);
+        if (i > pen_off[s] && pen_val[i] < pen_val[i - 1])
+          return fail(LBDD_E_INVAL, "penalties of center %d decrease at pen_val[%lld]", s, (long long)i);
+      }
+      first.push_back(pen_val[pen_off[s]]);
+    }
+    penalty = first.data();
+  }
   int64_t total = 0;
   for (int32_t s = 0; s < k; ++s) {
     if (capacity[s] < 0) return fail(LBDD_E_INVAL, "capacity[%d]=%d < 0", s, capacity[s]);
@@ -156,6 +177,8 @@ int create_instance(int32_t k, int64_t n, const int32_t *cm, const int32_t *capa
   if (e == hipSuccess) e = dalloc(&h->best, (size_t)k * k * lbdd::BEST_M, h->st);
   if (e == hipSuccess) e = dalloc(&h->meta, (size_t)k * k, h->st);
   if (e == hipSuccess) e = dalloc(&h->thr, (size_t)k * k, h->st);
+  if (table && e == hipSuccess) e = dalloc(&h->poff, (size_t)k + 1, h->st);
+  if (table && e == hipSuccess) e = dalloc(&h->pval, (size_t)pen_off[k], h->st);
   if (e != hipSuccess) { release(h); return hip_fail(e, "device allocation"); }
 
   // setup scratch: the unpermuted CM (host input only), sort keys, a flag
@@ -194,6 +217,11 @@ int create_instance(int32_t k, int64_t n, const int32_t *cm, const int32_t *capa
         (e = hipMemcpyAsync(h->pen, penalty, (size_t)k * 4, hipMemcpyHostToDevice, h->st)) != hipSuccess) {
       rc = hip_fail(e, "copy capacities/penalties"); break;
     }
+    if (table &&
+        ((e = hipMemcpyAsync(h->poff, pen_off, ((size_t)k + 1) * 8, hipMemcpyHostToDevice, h->st)) != hipSuccess ||
+         (e = hipMemcpyAsync(h->pval, pen_val, (size_t)pen_off[k] * 4, hipMemcpyHostToDevice, h->st)) != hipSuccess)) {
+      rc = hip_fail(e, "copy penalty tables"); break;
+    }
     if ((e = lbdd::launch_setup(k, n, cm_dev, h->cm, h->smin, h->order, bad, work, h->st)) != hipSuccess) {
       rc = hip_fail(e, "setup kernels"); break;
     }
@@ -229,12 +257,19 @@ extern "C" {
 
 int lbdd_create(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity,
                 const int32_t *penalty, uint32_t flags, void *hip_stream, lbdd_instance **out) {
-  return create_instance(k, n, cm, capacity, penalty, flags, hip_stream, false, out);
+  return create_instance(k, n, cm, capacity, penalty, nullptr, nullptr, flags, hip_stream, false, out);
 }
 
 int lbdd_create_strict(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity,
                        uint32_t flags, void *hip_stream, lbdd_instance **out) {
-  return create_instance(k, n, cm, capacity, nullptr, flags, hip_stream, true, out);
+  return create_instance(k, n, cm, capacity, nullptr, nullptr, nullptr, flags, hip_stream, true, out);
+}
+
+int lbdd_create_penalty_table(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity,
+                              const int64_t *pen_off, const int32_t *pen_val, uint32_t flags,
+                              void *hip_stream, lbdd_instance **out) {
+  if (!pen_off || !pen_val) return fail(LBDD_E_INVAL, "NULL penalty table");
+  return create_instance(k, n, cm, capacity, nullptr, pen_off, pen_val, flags, hip_stream, false, out);
 }
 
 int lbdd_centers(lbdd_instance *h, int32_t *k_graph) {
@@ -400,6 +435,30 @@ int lbdd_solve_batch(lbdd_instance **hs, int32_t m, void *hip_stream) {
     if (hs[i]->st != st) HIP_TRY(hipStreamWaitEvent(hs[i]->st, ev, 0), "hipStreamWaitEvent");
   }
   HIP_TRY(hipEventDestroy(ev), "hipEventDestroy");
+  return LBDD_OK;
+}
+
+size_t lbdd_road_cm_work_bytes(int32_t V, int32_t k) {
+  if (V < 1 || k < 1) return 0;
+  return lbdd::road_work_bytes(V, k);
+}
+
+int lbdd_road_cost_matrix(int32_t V, const int64_t *row_ptr, const int32_t *col, const int32_t *length,
+                          int32_t k, const int32_t *centers, int64_t n, const int32_t *units, int32_t *cm,
+                          void *work, void *hip_stream) {
+  g_err.clear();
+  if (V < 1) return fail(LBDD_E_INVAL, "V=%d < 1", V);
+  if (k < 1 || k > LBDD_MAX_K) return fail(LBDD_E_INVAL, "k=%d outside [1, %d]", k, LBDD_MAX_K);
+  if (n < 1 || n > LBDD_MAX_N) return fail(LBDD_E_INVAL, "n=%lld outside [1, 2^31-1]", (long long)n);
+  if (!row_ptr || !col || !length || !centers || !units || !cm || !work)
+    return fail(LBDD_E_INVAL, "NULL argument");
+  const int rc = lbdd::road_cost_matrix(V, row_ptr, col, length, k, centers, n, units, cm, work,
+                                        static_cast<hipStream_t>(hip_stream));
+  if (rc < 0) return hip_fail(static_cast<hipError_t>(-rc), "road network kernels");
+  if (rc == 1)
+    return fail(LBDD_E_INVAL, "road network: offsets not starting at 0 or decreasing, a vertex index "
+                              "outside [0, V) or an arc length outside [0, 2^30)");
+  if (rc == 2) return fail(LBDD_E_INVAL, "some unit is unreachable from some center, or 2^30 or more away");
   return LBDD_OK;
 }
 

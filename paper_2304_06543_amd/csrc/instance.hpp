@@ -33,6 +33,8 @@ struct lbdd_instance {
   uint64_t *best = nullptr;
   uint8_t *meta = nullptr;
   uint64_t *thr = nullptr;
+  int64_t *poff = nullptr;              // penalty tables (null: constant penalties)
+  int32_t *pval = nullptr;
 
   lbdd::InstView view() const {
     lbdd::InstView v;
@@ -40,6 +42,7 @@ struct lbdd_instance {
     v.assign = assign; v.load = load; v.members = members; v.slot = slot; v.W = W; v.Wh = Wh;
     v.best = best; v.meta = meta; v.thr = thr;
     v.scalars = scalars;
+    v.poff = poff; v.pval = pval;
     return v;
   }
 };

@@ -60,6 +60,11 @@ struct InstView {
   uint64_t *thr;           // [k][k] a joining unit's key changes the list (or its
                            // flags) only if it is below this threshold
   int64_t *scalars;        // [SC_COUNT] objective, progress, status, counters
+  // penalty function per center as a table (null: the constant pen[s]): the
+  // j-th unit beyond the capacity of s pays pval[poff[s] + min(j, len) - 1],
+  // len = poff[s + 1] - poff[s] >= 1
+  const int64_t *poff;     // [k + 1]
+  const int32_t *pval;     // [poff[k]]
 };
 
 // Bounded best-transfer lists (the paper's BestTransHeap of an ordered center

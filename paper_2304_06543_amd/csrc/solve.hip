@@ -3,7 +3,8 @@
 // Each iteration r (row r of the permuted cost matrix is the r-th unit of the
 // MinDistance order):
 //   allot     the unit goes to its most suitable center s; the objective grows
-//             by CM + (s full ? pen[s] : 0); its k-1 transfer keys are
+//             by CM + (s full ? the penalty of its next unit beyond
+//             capacity : 0); its k-1 transfer keys are
 //             min-inserted into row s of the best-transfer table W.
 //   cycle     Negative Cycle Refinement (Algorithm 1) with anchor s, on the
 //             NCyc split graph built on the fly from W.  Skipped exactly when
@@ -572,6 +573,15 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
   return conv;
 }
 
+// Penalty of the j-th unit (j >= 1) beyond the capacity of center s: the
+// constant pen[s], or the j-th value of the center's table (its last value
+// for every later unit).
+__device__ inline int64_t penalty_at(const InstView &I, const Lds &L, int s, int64_t j) {
+  if (!I.pval) return L.pen[s];
+  const int64_t b = I.poff[s], len = I.poff[s + 1] - b;
+  return I.pval[b + (j < len ? j : len) - 1];
+}
+
 // Label of s_in from the center labels (dist, hop) of a search from s.
 // s_in has no out-edges, so the center labels do not depend on its in-edges
 // (cycle mode: W[u][s]; path mode: the penalty difference).  In synchronous
@@ -583,6 +593,10 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
 __device__ __forceinline__ void sin_from_labels(const InstView &I, const Lds &L, int s, int mode) {
   const int k = I.k;
   const int tid = threadIdx.x;
+  // path mode: a unit leaving the anchor saves what its last unit beyond
+  // capacity pays (the anchor is overloaded whenever a path search runs)
+  const int64_t q_anchor =
+      mode == 0 ? 0 : penalty_at(I, L, s, L.load[s] > L.cap[s] ? (int64_t)L.load[s] - L.cap[s] : 1);
   auto in_weight = [&](int u, int64_t &w) -> bool {
     if (u == s || L.dist[u] == DIST_NONE) return false;
     if (mode == 0) {
@@ -590,7 +604,8 @@ __device__ __forceinline__ void sin_from_labels(const InstView &I, const Lds &L,
       if (key == KEY_NONE) return false;
       w = key_delta(key);
     } else {
-      w = (int64_t)(L.load[u] >= L.cap[u] ? L.pen[u] : 0) - L.pen[s];
+      // what one more unit at u would pay, minus what the anchor saves
+      w = (L.load[u] >= L.cap[u] ? penalty_at(I, L, u, (int64_t)L.load[u] - L.cap[u] + 1) : 0) - q_anchor;
     }
     return true;
   };
@@ -969,7 +984,7 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
         I.members[(int64_t)s * I.n + ld] = (int32_t)r;
         I.slot[r] = ld;
         L.load[s] = ld + 1;
-        S.obj += (int64_t)row[s] + (vac ? 0 : L.pen[s]);
+        S.obj += (int64_t)row[s] + (vac ? 0 : penalty_at(I, L, s, (int64_t)ld - L.cap[s] + 1));
       }
       const int ins = join_center(I, L, S, (int)r, s, (int)(r & 1));   // contains a barrier
       if (I.strict && L.load[s] == L.cap[s]) {

@@ -35,7 +35,8 @@ EXPORTS = ("lbdd_create", "lbdd_solve", "lbdd_solve_iters", "lbdd_solve_batch", 
            "lbdd_best_transfers", "lbdd_server_create", "lbdd_server_submit",
            "lbdd_server_poll", "lbdd_server_wait", "lbdd_server_result", "lbdd_server_stats",
            "lbdd_server_destroy", "lbdd_set_option", "lbdd_get_option", "lbdd_tune_search",
-           "lbdd_tune_best_transfers", "lbdd_create_strict", "lbdd_centers")
+           "lbdd_tune_best_transfers", "lbdd_create_strict", "lbdd_centers",
+           "lbdd_create_penalty_table", "lbdd_road_cm_work_bytes", "lbdd_road_cost_matrix")
 JOB_QUEUED, JOB_RUNNING, JOB_DONE = 0, 1, 2
 SERVER_STATS = ("submitted", "admitted", "finished", "failed", "kernel_launches",
                 "peak_jobs", "peak_bytes", "bytes_now", "workers")
@@ -85,6 +86,9 @@ def load(path: str = LIB_PATH):
         "lbdd_tune_best_transfers": ([I32, I64, P, P, P, P, P, I32, P, P, P], C.c_int),
         "lbdd_create_strict": ([I32, I64, P, P, U32, P, C.POINTER(P)], C.c_int),
         "lbdd_centers": ([P, C.POINTER(I32)], C.c_int),
+        "lbdd_create_penalty_table": ([I32, I64, P, P, P, P, U32, P, C.POINTER(P)], C.c_int),
+        "lbdd_road_cm_work_bytes": ([I32, I32], C.c_size_t),
+        "lbdd_road_cost_matrix": ([I32, P, P, P, I32, P, I64, P, P, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -141,15 +145,18 @@ def _create_args(cm, capacity, penalty):
 class Instance:
     """One LBDD instance living on the GPU (lbdd_create ... lbdd_destroy)."""
 
-    def __init__(self, cm, capacity, penalty=None, stream=None, strict: bool = False):
-        """penalty is required unless strict (strict-LBDD, lbdd_create_strict,
-        which takes none)."""
+    def __init__(self, cm, capacity, penalty=None, stream=None, strict: bool = False,
+                 pen_table=None):
+        """penalty (one constant per center) is required unless strict
+        (strict-LBDD, lbdd_create_strict, which takes none) or pen_table =
+        (offsets[k+1], values) gives a penalty function per center
+        (lbdd_create_penalty_table)."""
         lib = load()
         self._lib = lib
         self._h = C.c_void_p()
-        if strict:
-            if penalty is not None:
-                raise ValueError("strict-LBDD takes no penalties")
+        if strict or pen_table is not None:
+            if penalty is not None or (strict and pen_table is not None):
+                raise ValueError("give one of penalty, pen_table, strict")
             k, n, ptr, flags, cap, _, keep = _create_args(cm, capacity, capacity)
         else:
             if penalty is None:
@@ -160,6 +167,15 @@ class Instance:
         if strict:
             _check(lib.lbdd_create_strict(k, n, ptr, cap.ctypes.data_as(C.c_void_p), flags,
                                           self._stream, C.byref(self._h)))
+        elif pen_table is not None:
+            off = np.ascontiguousarray(pen_table[0], dtype=np.int64)
+            val = _host_i32(pen_table[1])
+            if off.shape != (k + 1,) or val.shape != (int(off[-1]),):
+                raise ValueError("pen_table needs k + 1 offsets and offsets[k] values")
+            _check(lib.lbdd_create_penalty_table(k, n, ptr, cap.ctypes.data_as(C.c_void_p),
+                                                 off.ctypes.data_as(C.c_void_p),
+                                                 val.ctypes.data_as(C.c_void_p), flags,
+                                                 self._stream, C.byref(self._h)))
         else:
             _check(lib.lbdd_create(k, n, ptr, cap.ctypes.data_as(C.c_void_p),
                                    pen.ctypes.data_as(C.c_void_p), flags, self._stream,
@@ -246,6 +262,27 @@ def solve(cm, capacity, penalty, stream=None):
     with Instance(cm, capacity, penalty, stream) as inst:
         inst.solve()
         return inst.objective(), inst.assignment()
+
+
+def road_cost_matrix(row_ptr, col, length, centers, units, work=None, stream=None):
+    """Cost matrix [n][k] int32 (a torch cuda tensor) from a road network given
+    as torch cuda tensors: row_ptr int64 [V+1], col and length int32 [E],
+    centers int32 [k], units int32 [n] (lbdd_road_cost_matrix)."""
+    import torch
+    lib = load()
+    for name, t, dt in (("row_ptr", row_ptr, torch.int64), ("col", col, torch.int32),
+                        ("length", length, torch.int32), ("centers", centers, torch.int32),
+                        ("units", units, torch.int32)):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous cuda tensor of {dt}")
+    V, k, n = row_ptr.numel() - 1, centers.numel(), units.numel()
+    if work is None:
+        work = torch.empty(lib.lbdd_road_cm_work_bytes(V, k), dtype=torch.uint8, device=row_ptr.device)
+    cm = torch.empty((n, k), dtype=torch.int32, device=row_ptr.device)
+    _check(lib.lbdd_road_cost_matrix(V, row_ptr.data_ptr(), col.data_ptr(), length.data_ptr(), k,
+                                     centers.data_ptr(), n, units.data_ptr(), cm.data_ptr(),
+                                     work.data_ptr(), _stream_ptr(stream)))
+    return cm
 
 
 def solve_strict(cm, capacity, stream=None):
