@@ -109,6 +109,53 @@ def run_batch(m, lbdd, L, torch, dev):
             "identical_to_plain": objs == plain_obj, "_objectives": objs}
 
 
+def run_scan_batch(m, reps, lbdd, L, torch, dev, stream):
+    """The batched scan over the first m instances of the batched workload
+    (every unit at its cheapest center, rank = unit index): the whole call
+    (descriptors, grouping, scan) and the streaming pass alone (grouping
+    reused), as aggregate GB/s of algorithmic bytes."""
+    import numpy as np
+    log(f"bench: batched scan over the first {m} instances of the batched workload")
+    insts = [L.make_batch_instance(sp) for sp in L.batch_specs()[:m]]
+    cms = [torch.from_numpy(i.cm).to(dev) for i in insts]
+    asg = [torch.argmin(c, dim=1).to(torch.int32).contiguous() for c in cms]
+    rks = [torch.arange(i.n, dtype=torch.int32, device=dev) for i in insts]
+    work = torch.empty(lbdd.best_transfers_batch_work_bytes(cms), dtype=torch.uint8, device=dev)
+    Ws = lbdd.best_transfers_batch(cms, asg, rks, work=work, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lbdd.best_transfers_batch(cms, asg, rks, Ws=Ws, work=work, stream=stream)
+    torch.cuda.synchronize()
+    call_ms = (time.perf_counter() - t0) * 1e3 / reps
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        lbdd.best_transfers_batch(cms, asg, rks, Ws=Ws, work=work, stream=stream, reuse_grouping=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    kern_ms = e0.elapsed_time(e1) / reps
+    kbytes = sum(i.n * (4 * i.k + 8) + 8 * i.k * i.k for i in insts)
+    cbytes = kbytes + sum(i.n * 8 for i in insts)      # + the allotment and ranks read by the grouping
+    same = True
+    for j in (0, m - 1):                              # spot check against the single scan
+        W1 = lbdd.best_transfers(cms[j], asg[j], rks[j], stream=stream)
+        same = same and bool(torch.equal(W1, Ws[j]))
+    out = {"workload": f"first {m} instances of the batched workload (k~U{{16..256}}, n log-uniform "
+                       f"[1e4,2e5]), every unit at its cheapest center",
+           "instances": m, "instances_with_16B_rows": sum(1 for i in insts if i.k % 4 == 0),
+           "call_ms": round(call_ms, 4), "call_bytes": cbytes,
+           "call_achieved": round(cbytes / (call_ms / 1e3) / 1e9, 1),
+           "kernel_ms": round(kern_ms, 4), "kernel_bytes": kbytes,
+           "kernel_achieved": round(kbytes / (kern_ms / 1e3) / 1e9, 1),
+           "kernel_frac": round(kbytes / (kern_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+           "tables_equal_single_scans": same}
+    log(f"bench: batched scan call {call_ms:.3f} ms, streaming pass {kern_ms:.3f} ms "
+        f"-> {out['kernel_achieved']} GB/s")
+    return out
+
+
 def _oracle_solve(args):
     """Worker of the instance-parallel CPU baseline: one whole oracle solve."""
     import oracle
@@ -196,6 +243,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-scan", action="store_true")
     ap.add_argument("--scan-reps", type=int, default=10)
+    ap.add_argument("--scan-batch", type=int, default=16,
+                    help="instances of the batched workload scanned together by the batched scan (0: skip)")
     ap.add_argument("--batch", type=int, default=16,
                     help="instances of the batched workload to compare batched vs plain (0: skip)")
     ap.add_argument("--serve", type=int, default=100,
@@ -340,6 +389,8 @@ def main():
         log(f"bench: scan call {ms:.3f} ms -> {scan['achieved']} GB/s; scan kernel {ms_k:.3f} ms "
             f"-> {scan['kernel_achieved']} GB/s")
         del cmb, W, work
+        if args.scan_batch > 0:
+            scan["batch"] = run_scan_batch(args.scan_batch, args.scan_reps, lbdd, L, torch, dev, stream)
 
     if args.copy_calib:
         # plain elementwise kernel of known traffic: reads 1 GiB, writes 1 GiB

@@ -322,6 +322,32 @@ int lbdd_best_transfers(int32_t k, int64_t n, const int32_t *cm, const int32_t *
                         const int32_t *rank, uint64_t *W, void *work, uint32_t flags,
                         void *hip_stream);
 
+/* The tables of many allotments at once (the batched form of the scan above;
+ * LBDD_SCAN_REUSE_GROUPING is defined there):
+ * item i has k[i] centers (1 <= k[i] <= LBDD_MAX_K) and n[i] >= 0 units, and
+ * cm[i], assign[i], rank[i], W[i] as lbdd_best_transfers (device pointers;
+ * the four pointer arrays and k, n are host arrays of m entries).  One
+ * sequence of launches serves all items: a clear of every table, grouping
+ * passes over the concatenated units and one streaming pass over the
+ * concatenated rows, split evenly over the resident workgroups; the lane
+ * layout follows each item's k.  Items with k % 4 != 0 (or a cm that is not
+ * 16-byte aligned) use 4-byte loads and k <= 512; others k <= 2048.
+ *   work    device scratch of lbdd_best_transfers_batch_work_bytes(m, k, n)
+ *           bytes (0 for invalid sizes); holds the item descriptors and the
+ *           groupings when the call returns
+ *   flags   LBDD_SCAN_REUSE_GROUPING: work holds the descriptors and
+ *           groupings of a previous call with the same arguments (e.g. after
+ *           the cost matrices changed), so only the tables are cleared and
+ *           the matrices scanned: fully asynchronous
+ * Without the flag the call waits for earlier work on `hip_stream`, copies
+ * the item descriptors into work, then enqueues the kernels asynchronously.
+ * Errors: LBDD_E_INVAL (sizes, NULL, unknown flags, an item beyond the
+ * layouts above), LBDD_E_DEVICE. */
+size_t lbdd_best_transfers_batch_work_bytes(int32_t m, const int32_t *k, const int64_t *n);
+int lbdd_best_transfers_batch(int32_t m, const int32_t *k, const int64_t *n, const int32_t *const *cm,
+                              const int32_t *const *assign, const int32_t *const *rank, uint64_t *const *W,
+                              void *work, uint32_t flags, void *hip_stream);
+
 /* ---- autotuner -------------------------------------------------------------
  * Both calls time choices that leave every result unchanged and record the
  * fastest in a lock-guarded table of this process.  An instance takes its

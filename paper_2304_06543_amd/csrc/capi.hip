@@ -19,6 +19,7 @@
 #include "instance.hpp"
 #include "lbdd_dev.hpp"
 #include "road.hpp"
+#include "scan_batch.hpp"
 
 namespace {
 
@@ -459,6 +460,33 @@ int lbdd_road_cost_matrix(int32_t V, const int64_t *row_ptr, const int32_t *col,
     return fail(LBDD_E_INVAL, "road network: offsets not starting at 0 or decreasing, a vertex index "
                               "outside [0, V) or an arc length outside [0, 2^30)");
   if (rc == 2) return fail(LBDD_E_INVAL, "some unit is unreachable from some center, or 2^30 or more away");
+  return LBDD_OK;
+}
+
+size_t lbdd_best_transfers_batch_work_bytes(int32_t m, const int32_t *k, const int64_t *n) {
+  if (m < 1 || !k || !n) return 0;
+  for (int32_t i = 0; i < m; ++i)
+    if (k[i] < 1 || k[i] > LBDD_MAX_K || n[i] < 0 || n[i] > LBDD_MAX_N) return 0;
+  return lbdd::batch_scan_work_bytes(m, k, n);
+}
+
+int lbdd_best_transfers_batch(int32_t m, const int32_t *k, const int64_t *n, const int32_t *const *cm,
+                              const int32_t *const *assign, const int32_t *const *rank, uint64_t *const *W,
+                              void *work, uint32_t flags, void *hip_stream) {
+  g_err.clear();
+  if (m < 1 || !k || !n || !cm || !assign || !rank || !W || !work) return fail(LBDD_E_INVAL, "bad argument");
+  if (flags & ~LBDD_SCAN_REUSE_GROUPING) return fail(LBDD_E_INVAL, "unknown flags 0x%x", flags);
+  for (int32_t i = 0; i < m; ++i) {
+    if (k[i] < 1 || k[i] > LBDD_MAX_K) return fail(LBDD_E_INVAL, "item %d: k=%d outside [1, %d]", i, k[i], LBDD_MAX_K);
+    if (n[i] < 0 || n[i] > LBDD_MAX_N) return fail(LBDD_E_INVAL, "item %d: n=%lld outside [0, 2^31-1]", i, (long long)n[i]);
+    if (!W[i] || (n[i] > 0 && (!cm[i] || !assign[i] || !rank[i]))) return fail(LBDD_E_INVAL, "item %d: NULL array", i);
+    if (lbdd::batch_scan_np(k[i], cm[i]) > 8)
+      return fail(LBDD_E_INVAL, "item %d: k=%d needs more than 8 column groups per lane (4-byte loads when "
+                                "k %% 4 != 0); scan it with lbdd_best_transfers", i, k[i]);
+  }
+  HIP_TRY(lbdd::launch_batch_scan(m, k, n, cm, assign, rank, W, work, flags & LBDD_SCAN_REUSE_GROUPING,
+                                  static_cast<hipStream_t>(hip_stream)),
+          "batched scan kernels");
   return LBDD_OK;
 }
 

@@ -36,7 +36,8 @@ EXPORTS = ("lbdd_create", "lbdd_solve", "lbdd_solve_iters", "lbdd_solve_batch", 
            "lbdd_server_poll", "lbdd_server_wait", "lbdd_server_result", "lbdd_server_stats",
            "lbdd_server_destroy", "lbdd_set_option", "lbdd_get_option", "lbdd_tune_search",
            "lbdd_tune_best_transfers", "lbdd_create_strict", "lbdd_centers",
-           "lbdd_create_penalty_table", "lbdd_road_cm_work_bytes", "lbdd_road_cost_matrix")
+           "lbdd_create_penalty_table", "lbdd_road_cm_work_bytes", "lbdd_road_cost_matrix",
+           "lbdd_best_transfers_batch_work_bytes", "lbdd_best_transfers_batch")
 JOB_QUEUED, JOB_RUNNING, JOB_DONE = 0, 1, 2
 SERVER_STATS = ("submitted", "admitted", "finished", "failed", "kernel_launches",
                 "peak_jobs", "peak_bytes", "bytes_now", "workers")
@@ -89,6 +90,8 @@ def load(path: str = LIB_PATH):
         "lbdd_create_penalty_table": ([I32, I64, P, P, P, P, U32, P, C.POINTER(P)], C.c_int),
         "lbdd_road_cm_work_bytes": ([I32, I32], C.c_size_t),
         "lbdd_road_cost_matrix": ([I32, P, P, P, I32, P, I64, P, P, P, P], C.c_int),
+        "lbdd_best_transfers_batch_work_bytes": ([I32, P, P], C.c_size_t),
+        "lbdd_best_transfers_batch": ([I32, P, P, P, P, P, P, P, U32, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -331,6 +334,46 @@ def best_transfers(cm, assign, rank, W=None, work=None, stream=None, reuse_group
                                       SCAN_REUSE_GROUPING if reuse_grouping else 0,
                                       _stream_ptr(stream)))
     return W
+
+
+def best_transfers_batch_work_bytes(cms) -> int:
+    ks = np.array([c.shape[1] for c in cms], np.int32)
+    ns = np.array([c.shape[0] for c in cms], np.int64)
+    return int(load().lbdd_best_transfers_batch_work_bytes(len(cms), ks.ctypes.data_as(C.c_void_p),
+                                                           ns.ctypes.data_as(C.c_void_p)))
+
+
+def best_transfers_batch(cms, assigns, ranks, Ws=None, work=None, stream=None, reuse_grouping=False):
+    """Best-transfer tables of many allotments in one sequence of launches
+    (lbdd_best_transfers_batch).  cms[i] [n_i][k_i], assigns[i], ranks[i] [n_i]:
+    contiguous int32 torch cuda tensors.  Returns the list of tables (torch
+    int64 [k_i][k_i] holding the uint64 key bits).  reuse_grouping: `work`
+    holds the descriptors and groupings of a previous call with the same
+    arguments; only the tables are cleared and the matrices scanned."""
+    import torch
+    m = len(cms)
+    if not (m == len(assigns) == len(ranks)) or m == 0:
+        raise ValueError("need the same positive number of cms, assigns and ranks")
+    for t in (*cms, *assigns, *ranks):
+        if not (t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()):
+            raise ValueError("cm, assign and rank must be contiguous int32 cuda tensors")
+    ks = np.array([c.shape[1] for c in cms], np.int32)
+    ns = np.array([c.shape[0] for c in cms], np.int64)
+    if reuse_grouping and (Ws is None or work is None):
+        raise ValueError("reuse_grouping needs the tables and the work buffer of the earlier call")
+    if Ws is None:
+        Ws = [torch.empty((int(k), int(k)), dtype=torch.int64, device=cms[0].device) for k in ks]
+    lib = load()
+    if work is None:
+        work = torch.empty(max(best_transfers_batch_work_bytes(cms), 1), dtype=torch.uint8,
+                           device=cms[0].device)
+    ptrs = [(C.c_void_p * m)(*[t.data_ptr() for t in ts]) for ts in (cms, assigns, ranks, Ws)]
+    _check(lib.lbdd_best_transfers_batch(m, ks.ctypes.data_as(C.c_void_p), ns.ctypes.data_as(C.c_void_p),
+                                         *[C.cast(p, C.c_void_p) for p in ptrs],
+                                         C.c_void_p(work.data_ptr()),
+                                         SCAN_REUSE_GROUPING if reuse_grouping else 0,
+                                         _stream_ptr(stream)))
+    return Ws
 
 
 def tune_search(cm, capacity, penalty, iters: int, stream=None):

@@ -1,0 +1,94 @@
+"""GPU parity of the batched best-transfer scan (definition of Gamma, Section
+3.2, condensed per center pair) against the oracle's plain definition and the
+single-instance scan, bit-exact.  All calls go through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+import lbdd_inputs as L
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    import paper_2304_06543_amd.lbdd as lb
+    lb.load()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return lb
+
+
+def _items(seed, shapes):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k, n in shapes:
+        cm = rng.integers(0, [4, 1000, 2**30][len(out) % 3], size=(n, k)).astype(np.int32)
+        assign = rng.integers(-1, k, size=n).astype(np.int32)      # -1: not allotted
+        rank = rng.permutation(n).astype(np.int32)
+        out.append((cm, assign, rank))
+    return out
+
+
+def _run(lb, items, reuse_check=True):
+    import torch
+    cms = [torch.from_numpy(c).cuda() for c, _, _ in items]
+    asg = [torch.from_numpy(a).cuda() for _, a, _ in items]
+    rks = [torch.from_numpy(r).cuda() for _, _, r in items]
+    work = torch.empty(max(lb.best_transfers_batch_work_bytes(cms), 1), dtype=torch.uint8, device="cuda")
+    Ws = lb.best_transfers_batch(cms, asg, rks, work=work)
+    got = [W.cpu().numpy().view(np.uint64) for W in Ws]
+    if reuse_check:                                   # scan only: same arguments, same grouping
+        for W in Ws:
+            W.fill_(0)
+        Ws2 = lb.best_transfers_batch(cms, asg, rks, Ws=Ws, work=work, reuse_grouping=True)
+        for a, b in zip(got, Ws2):
+            assert np.array_equal(a, b.cpu().numpy().view(np.uint64))
+    return got, cms, asg, rks
+
+
+SHAPES = [
+    [(1, 10), (3, 0), (4, 1), (16, 700), (17, 5000), (64, 3000), (100, 20000), (128, 999)],
+    [(255, 4000), (256, 7000), (500, 3000), (512, 2500), (2048, 300), (33, 12345)],
+    [(5, 1), (7, 9000), (200, 1), (2, 2)],
+]
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_batch_equals_definition(lb, case):
+    items = _items(100 + case, SHAPES[case])
+    say("batch scan", case, SHAPES[case])
+    got, *_ = _run(lb, items)
+    for (cm, a, r), W in zip(items, got):
+        assert np.array_equal(W, oracle.best_transfers(cm, a, r.astype(np.int64)))
+
+
+def test_batched_workload_equals_single_scans(lb):
+    """The first 16 instances of the batched workload, every unit at its
+    cheapest center, rank = unit index: each table equals the single scan's."""
+    import torch
+    insts = [L.make_batch_instance(sp) for sp in L.batch_specs()[:16]]
+    items = [(i.cm, np.argmin(i.cm, axis=1).astype(np.int32), np.arange(i.n, dtype=np.int32))
+             for i in insts]
+    say("batch scan C4[:16]")
+    got, cms, asg, rks = _run(lb, items)
+    for j, (c, a, r) in enumerate(zip(cms, asg, rks)):
+        W = lb.best_transfers(c, a, r).cpu().numpy().view(np.uint64)
+        assert np.array_equal(got[j], W), j
+    small = min(range(16), key=lambda j: insts[j].n * insts[j].k)
+    cm, a, r = items[small]
+    assert np.array_equal(got[small], oracle.best_transfers(cm, a, r.astype(np.int64)))
+
+
+def test_batch_rejects_unsupported_layouts(lb):
+    import torch
+    c = torch.zeros((4, 513), dtype=torch.int32, device="cuda")     # 4-byte loads, 9 groups per lane
+    a = torch.zeros(4, dtype=torch.int32, device="cuda")
+    with pytest.raises(lb.LbddError):
+        lb.best_transfers_batch([c], [a], [a])
