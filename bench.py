@@ -116,8 +116,13 @@ def run_scan_batch(m, reps, lbdd, L, torch, dev, stream):
     reused), as aggregate GB/s of algorithmic bytes."""
     import numpy as np
     log(f"bench: batched scan over the first {m} instances of the batched workload")
-    insts = [L.make_batch_instance(sp) for sp in L.batch_specs()[:m]]
-    cms = [torch.from_numpy(i.cm).to(dev) for i in insts]
+    insts, cms = [], []
+    for j, sp in enumerate(L.batch_specs()[:m]):
+        insts.append(L.make_batch_instance(sp))
+        cms.append(torch.from_numpy(insts[-1].cm).to(dev))
+        insts[-1].cm = None                            # the device copy is enough
+        if (j + 1) % 32 == 0:
+            log(f"bench: batched scan: {j + 1} instances on the device")
     asg = [torch.argmin(c, dim=1).to(torch.int32).contiguous() for c in cms]
     rks = [torch.arange(i.n, dtype=torch.int32, device=dev) for i in insts]
     work = torch.empty(lbdd.best_transfers_batch_work_bytes(cms), dtype=torch.uint8, device=dev)
