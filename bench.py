@@ -37,6 +37,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_cpu() -> str:
+    """The host's CPU model and logical core count."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical cores"
+
+
 def recorded_traffic(kernel: str):
     """HBM bytes per launch of `kernel` on this benchmark's workload, from the
     committed counter summary (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by
@@ -334,6 +348,15 @@ def main():
     parity = all(o == gold["objective"] for o in objs)
     log(f"bench: {ms_per_step:.1f} ms/step, solve kernel {np.mean(solve_ms):.1f} ms, "
         f"objective parity {parity}, stats {stats}")
+    # end to end from a host cost matrix (PCIe copy included): context only
+    tc = time.perf_counter()
+    h = lbdd.Instance(inst.cm, inst.cap, inst.pen, stream=stream)
+    h.solve()
+    e2e_obj = h.objective()
+    h.assignment()
+    h.close()
+    e2e_ms = (time.perf_counter() - tc) * 1e3
+    log(f"bench: end to end from host memory {e2e_ms:.1f} ms")
 
     nbytes = solve_bytes(inst.k, stats)
     kern_s = float(np.mean(solve_ms)) / 1e3
@@ -394,6 +417,25 @@ def main():
         log(f"bench: scan call {ms:.3f} ms -> {scan['achieved']} GB/s; scan kernel {ms_k:.3f} ms "
             f"-> {scan['kernel_achieved']} GB/s")
         del cmb, W, work
+        # what a plain device-to-device copy of the same size reaches on this GPU
+        src = torch.empty(big.n * big.k, dtype=torch.int32, device=dev)
+        src.fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.scan_reps):
+            dst.copy_(src)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        cms_ = e0.elapsed_time(e1) / args.scan_reps
+        copy_gbs = 2 * src.numel() * 4 / (cms_ / 1e3) / 1e9
+        scan["copy_ceiling"] = {"kernel": "torch device-to-device copy of 2 GB (2 GB read + 2 GB written)",
+                                "ms": round(cms_, 4), "achieved": round(copy_gbs, 1),
+                                "frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4)}
+        scan["kernel_frac_of_copy"] = round(scan["kernel_achieved"] / copy_gbs, 4)
+        log(f"bench: copy ceiling {copy_gbs:.0f} GB/s")
+        del src, dst
         if args.scan_batch > 0:
             scan["batch"] = run_scan_batch(args.scan_batch, args.scan_reps, lbdd, L, torch, dev, stream)
 
@@ -502,8 +544,20 @@ def main():
         dt = time.perf_counter() - tc
         cpu = {"value": round(1.0 / dt, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
                "sample": f"one whole solve of the k=100 n=100000 instance ({dt:.1f} s); "
-                         f"objective {'matches' if r.objective == gold['objective'] else 'DIFFERS'}"}
+                         f"objective {'matches' if r.objective == gold['objective'] else 'DIFFERS'}",
+               "host": host_cpu()}
         log(f"bench: oracle {dt:.1f} s")
+        # the para-ASRAL-style build of the same oracle: threads for the
+        # Gamma-structure updates, split graphs and Bellman-Ford rounds
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        tc = time.perf_counter()
+        rp = oracle.solve(*inst.arrays(), lib=oracle.load_para())
+        dtp = time.perf_counter() - tc
+        cpu["para"] = {"value": round(1.0 / dtp, 5), "unit": "solves/s", "cores": threads,
+                       "kind": "para-ASRAL-style threaded oracle (OpenMP, same results)",
+                       "sample": f"one whole solve of the same instance ({dtp:.1f} s); objective "
+                                 f"{'matches' if rp.objective == gold['objective'] else 'DIFFERS'}"}
+        log(f"bench: para oracle {dtp:.1f} s on {threads} threads")
         if strict is not None:
             tc = time.perf_counter()
             rs = oracle.solve_strict(inst.cm, inst.cap)
@@ -527,6 +581,9 @@ def main():
                                "capacities total 0.95n, penalties U{100..1000})",
                    "k": inst.k, "n": inst.n, "parallelism": "one instance per GPU"},
         "parity": {"objective_matches_oracle": parity, "objective": objs[-1]},
+        "end_to_end_host_cm": {"ms": round(e2e_ms, 3), "objective_matches_oracle": e2e_obj == gold["objective"],
+                               "what": "create from a host CM (PCIe copy) + setup + solve + objective "
+                                       "and assignment read back"},
         "stats": stats,
         "roofline": roofline,
         "scan": scan,

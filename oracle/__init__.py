@@ -5,8 +5,10 @@ the benchmark's CPU-baseline leg may import it.  The product path never does;
 it shares no code with the HIP library.
 
 ``build()`` compiles ``asral_oracle.c`` with gcc into ``_asral_oracle.so``
-beside it.  Every function below cites the passage of the paper it follows in
-the C source's header.
+beside it, and ``build_para()`` the same source with OpenMP into
+``_asral_para.so``: the para-ASRAL-style CPU baseline (Section 3.6), whose
+results are identical.  Every function below cites the passage of the paper it
+follows in the C source's header.
 """
 from __future__ import annotations
 
@@ -20,6 +22,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(_HERE, "asral_oracle.c")
 LIB = os.path.join(_HERE, "_asral_oracle.so")
+PARA_LIB = os.path.join(_HERE, "_asral_para.so")
 
 TRACE_W = 8
 STATS_N = 8
@@ -31,13 +34,29 @@ E_INVAL, E_NOMEM, E_NEGCYCLE = -1, -2, -5
 
 def build(src: str = SRC, out: str = LIB, extra=()) -> str:
     """Compile the oracle with gcc (-O2, strict IEEE irrelevant: integer only)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-Wno-unknown-pragmas", "-fPIC", "-shared",
            *extra, "-o", out, src]
     subprocess.run(cmd, check=True)
     return out
 
 
+def build_para(out: str = PARA_LIB) -> str:
+    """The para-ASRAL-style build: the same source with OpenMP threads."""
+    return build(out=out, extra=("-fopenmp",))
+
+
 _lib = None
+_para = None
+
+
+def load_para():
+    """The threaded build (thread count from OMP_NUM_THREADS)."""
+    global _para
+    if _para is None:
+        if not os.path.exists(PARA_LIB):
+            build_para()
+        _para = _load(PARA_LIB)
+    return _para
 
 
 def _load(path: str = LIB):

@@ -62,6 +62,19 @@
 #define ORC_E_NOMEM (-2)
 #define ORC_E_NEGCYCLE (-5)
 
+/* Built with -fopenmp (PARA = 1) the same code is the para-ASRAL-style CPU
+ * baseline (Section 3.6): the per-heap updates of the Gamma data structure,
+ * the split-graph construction and each Bellman-Ford round's targets run in
+ * threads when k >= PARA_MIN_K.  Every threaded loop writes disjoint data and
+ * reads only what the loop does not write, so both builds give identical
+ * results.  The plain build (no -fopenmp) ignores the pragmas.              */
+#ifdef _OPENMP
+#define PARA 1
+#else
+#define PARA 0
+#endif
+#define PARA_MIN_K 64
+
 #define KEY_NONE UINT64_MAX
 #define DIST_NONE INT64_MAX
 #define CM_LIMIT (1 << 30)
@@ -249,6 +262,7 @@ static void build_split_graph(int32_t k, const uint64_t *W, int32_t anchor, int 
                               int64_t *wt, uint8_t *has) {
     const int32_t K1 = k + 1;
     memset(has, 0, (size_t)K1 * K1);
+    #pragma omp parallel for schedule(static) if(PARA && k >= PARA_MIN_K)
     for (int32_t u = 0; u < k; ++u) {
         for (int32_t v = 0; v < k; ++v) {
             if (u == v || v == anchor) continue;       /* nothing enters s*_out */
@@ -283,6 +297,8 @@ static int bellman_ford(int32_t K1, int32_t src, const int64_t *wt, const uint8_
     dist[src] = 0;
     for (int32_t t = 1; t <= K1; ++t) {
         int changed = 0;
+        /* each target's candidate reads only the previous round's labels */
+        #pragma omp parallel for schedule(static) reduction(|:changed) if(PARA && K1 > PARA_MIN_K)
         for (int32_t v = 0; v < K1; ++v) {
             int64_t cand = DIST_NONE;
             int32_t arg = -1;
@@ -404,14 +420,16 @@ static uint64_t heap_top(orc_state *S, int32_t u, int32_t v) {
 /* unit d has just been placed at center u: add its k-1 transfer edges */
 static int heaps_insert_unit(orc_state *S, int64_t d, int32_t u) {
     const int32_t *row = S->cm + d * (int64_t)S->k;
+    int rc = ORC_OK;
+    /* the k-1 heaps are distinct: the para-ASRAL build updates them in
+     * threads (Section 3.6, updating the Gamma data structure in parallel) */
+    #pragma omp parallel for schedule(static) reduction(|:rc) if(PARA && S->k >= PARA_MIN_K)
     for (int32_t v = 0; v < S->k; ++v) {
         if (v == u) continue;
-        int rc = heap_push(&S->H[(int64_t)u * S->k + v],
-                           pack_key((int64_t)row[v] - row[u], S->rank[d]));
-        if (rc) return rc;
-        S->stats[6]++;
+        rc |= heap_push(&S->H[(int64_t)u * S->k + v], pack_key((int64_t)row[v] - row[u], S->rank[d]));
     }
-    return ORC_OK;
+    S->stats[6] += S->k - 1;
+    return rc ? ORC_E_NOMEM : ORC_OK;
 }
 
 /* Key of moving one of the zero-cost dummy units of strict-LBDD (Appendix B)
@@ -420,6 +438,8 @@ static int heaps_insert_unit(orc_state *S, int64_t d, int32_t u) {
 #define DUMMY_KEY (((uint64_t)1u << 63) | 0xFFFFFFFEu)
 
 static void refresh_W(orc_state *S) {
+    /* rows touch disjoint heaps (lazy deletion pops only H[u][.]) */
+    #pragma omp parallel for schedule(static) if(PARA && S->k >= PARA_MIN_K)
     for (int32_t u = 0; u < S->k; ++u)
         for (int32_t v = 0; v < S->k; ++v) {
             uint64_t key = (u == v) ? KEY_NONE : heap_top(S, u, v);
