@@ -36,9 +36,21 @@ def _items(seed, shapes):
     return out
 
 
-def _run(lb, items, reuse_check=True):
+def _unaligned(c):
+    """A device copy of c whose rows start 4 bytes past a 16-byte boundary
+    (4-byte loads)."""
     import torch
-    cms = [torch.from_numpy(c).cuda() for c, _, _ in items]
+    buf = torch.empty(c.size + 1, dtype=torch.int32, device="cuda")
+    t = buf[1:].view(c.shape)
+    t.copy_(torch.from_numpy(c))
+    assert t.data_ptr() % 16 != 0 and t.is_contiguous()
+    return t
+
+
+def _run(lb, items, reuse_check=True, unaligned=()):
+    import torch
+    cms = [(_unaligned(c) if j in unaligned and c.size else torch.from_numpy(c).cuda())
+           for j, (c, _, _) in enumerate(items)]
     asg = [torch.from_numpy(a).cuda() for _, a, _ in items]
     rks = [torch.from_numpy(r).cuda() for _, _, r in items]
     work = torch.empty(max(lb.best_transfers_batch_work_bytes(cms), 1), dtype=torch.uint8, device="cuda")
@@ -62,9 +74,13 @@ SHAPES = [
 
 @pytest.mark.parametrize("case", range(3))
 def test_batch_equals_definition(lb, case):
+    """Every load mode: 16-byte rows (k % 4 == 0), realigned 16-byte blocks
+    (k % 4 != 0) and, for a few items copied to an unaligned address, 4-byte
+    loads."""
     items = _items(100 + case, SHAPES[case])
     say("batch scan", case, SHAPES[case])
-    got, *_ = _run(lb, items)
+    odd = tuple(j for j, (k, n) in enumerate(SHAPES[case]) if j % 2 and k <= 512)
+    got, *_ = _run(lb, items, unaligned=odd)
     for (cm, a, r), W in zip(items, got):
         assert np.array_equal(W, oracle.best_transfers(cm, a, r.astype(np.int64)))
 
@@ -88,7 +104,7 @@ def test_batched_workload_equals_single_scans(lb):
 
 def test_batch_rejects_unsupported_layouts(lb):
     import torch
-    c = torch.zeros((4, 513), dtype=torch.int32, device="cuda")     # 4-byte loads, 9 groups per lane
+    c = _unaligned(np.zeros((4, 514), np.int32))                   # 4-byte loads, 9 groups per lane
     a = torch.zeros(4, dtype=torch.int32, device="cuda")
     with pytest.raises(lb.LbddError):
         lb.best_transfers_batch([c], [a], [a])
