@@ -169,6 +169,7 @@ def run_scan_batch(m, reps, lbdd, L, torch, dev, stream):
            "kernel_ms": round(kern_ms, 4), "kernel_bytes": kbytes,
            "kernel_achieved": round(kbytes / (kern_ms / 1e3) / 1e9, 1),
            "kernel_frac": round(kbytes / (kern_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+           "kernel_traffic": recorded_traffic("bscan_kernel") if m == 16 else None,
            "tables_equal_single_scans": same}
     log(f"bench: batched scan call {call_ms:.3f} ms, streaming pass {kern_ms:.3f} ms "
         f"-> {out['kernel_achieved']} GB/s")
