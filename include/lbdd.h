@@ -2,7 +2,7 @@
  * lbdd.h -- C ABI of the MI355X (gfx950) ASRAL solver for Load Balanced Demand
  * Distribution under overload penalties (arXiv 2304.06543).
  *
- * Problem (Section 2.1, "Problem Statement"): given k service centers S, n
+ * Problem (Section 2.1, the problem statement): given k service centers S, n
  * demand units D, an integer cost matrix CM(d,s), a capacity c_s and a
  * penalty for every unit a center takes beyond its capacity, find a complete
  * allotment (every unit to exactly one center) with a small value of the
@@ -27,7 +27,7 @@
  *     synchronise with that stream.
  *   - A handle is not thread-safe; distinct handles are independent.
  *
- * Ties (the paper breaks them "arbitrarily"; this library fixes them):
+ * Ties (the paper leaves them open; this library fixes them):
  *   - a unit's most suitable center is the smallest index among its cheapest;
  *   - units are processed by (cheapest cost, unit index) ascending;
  *   - the best transfer of a center pair is the smallest transfer cost, then

@@ -26,8 +26,8 @@ with the same numpy.  Distances use only IEEE add, multiply, abs and sqrt
 (correctly rounded), and rounding is half-up (floor(x + 0.5)).
 
 Penalties are one constant per center, as in the paper's experiments (Section
-5, "For sake of easy interpretation ... each service center has a penalty
-value (chosen randomly) inside a range").  ``rising_penalties`` turns them into
+5: each center draws one penalty value at random from a stated range, in
+place of a general penalty function).  ``rising_penalties`` turns them into
 the general increasing penalty functions of the problem statement (Section 2),
 as one table per center.
 """
