@@ -341,8 +341,9 @@ int lbdd_best_transfers(int32_t k, int64_t n, const int32_t *cm, const int32_t *
  *           the matrices scanned: fully asynchronous
  * Without the flag the call waits for earlier work on `hip_stream`, copies
  * the item descriptors into work, then enqueues the kernels asynchronously.
- * Errors: LBDD_E_INVAL (sizes, NULL, unknown flags, an item beyond the
- * layouts above), LBDD_E_DEVICE. */
+ * Errors: LBDD_E_INVAL (sizes, m outside [1, LBDD_MAX_SCAN_ITEMS], NULL,
+ * unknown flags, an item beyond the layouts above), LBDD_E_DEVICE. */
+#define LBDD_MAX_SCAN_ITEMS 65535     /* items per lbdd_best_transfers_batch call */
 size_t lbdd_best_transfers_batch_work_bytes(int32_t m, const int32_t *k, const int64_t *n);
 int lbdd_best_transfers_batch(int32_t m, const int32_t *k, const int64_t *n, const int32_t *const *cm,
                               const int32_t *const *assign, const int32_t *const *rank, uint64_t *const *W,

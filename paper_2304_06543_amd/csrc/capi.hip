@@ -464,7 +464,7 @@ int lbdd_road_cost_matrix(int32_t V, const int64_t *row_ptr, const int32_t *col,
 }
 
 size_t lbdd_best_transfers_batch_work_bytes(int32_t m, const int32_t *k, const int64_t *n) {
-  if (m < 1 || !k || !n) return 0;
+  if (m < 1 || m > LBDD_MAX_SCAN_ITEMS || !k || !n) return 0;
   for (int32_t i = 0; i < m; ++i)
     if (k[i] < 1 || k[i] > LBDD_MAX_K || n[i] < 0 || n[i] > LBDD_MAX_N) return 0;
   return lbdd::batch_scan_work_bytes(m, k, n);
@@ -475,6 +475,7 @@ int lbdd_best_transfers_batch(int32_t m, const int32_t *k, const int64_t *n, con
                               void *work, uint32_t flags, void *hip_stream) {
   g_err.clear();
   if (m < 1 || !k || !n || !cm || !assign || !rank || !W || !work) return fail(LBDD_E_INVAL, "bad argument");
+  if (m > LBDD_MAX_SCAN_ITEMS) return fail(LBDD_E_INVAL, "m=%d items: at most %d per call", m, LBDD_MAX_SCAN_ITEMS);
   if (flags & ~LBDD_SCAN_REUSE_GROUPING) return fail(LBDD_E_INVAL, "unknown flags 0x%x", flags);
   for (int32_t i = 0; i < m; ++i) {
     if (k[i] < 1 || k[i] > LBDD_MAX_K) return fail(LBDD_E_INVAL, "item %d: k=%d outside [1, %d]", i, k[i], LBDD_MAX_K);
