@@ -435,21 +435,7 @@ def main():
                                 "ms": round(cms_, 4), "achieved": round(copy_gbs, 1),
                                 "frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4)}
         scan["kernel_frac_of_copy"] = round(scan["kernel_achieved"] / copy_gbs, 4)
-        # and a plain read of the same 2 GB (a sum: reads only)
-        acc = src.sum(dtype=torch.int64)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(args.scan_reps):
-            acc = src.sum(dtype=torch.int64)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        rms = e0.elapsed_time(e1) / args.scan_reps
-        read_gbs = src.numel() * 4 / (rms / 1e3) / 1e9
-        scan["read_ceiling"] = {"kernel": "torch sum over 2 GB of int32 (reads only)", "ms": round(rms, 4),
-                                "achieved": round(read_gbs, 1), "frac_of_peak": round(read_gbs / HBM_PEAK_GBS, 4)}
-        scan["kernel_frac_of_read"] = round(scan["kernel_achieved"] / read_gbs, 4)
-        log(f"bench: copy ceiling {copy_gbs:.0f} GB/s, read ceiling {read_gbs:.0f} GB/s")
-        del acc
+        log(f"bench: copy ceiling {copy_gbs:.0f} GB/s")
         del src, dst
         if args.scan_batch > 0:
             scan["batch"] = run_scan_batch(args.scan_batch, args.scan_reps, lbdd, L, torch, dev, stream)
