@@ -84,7 +84,7 @@ struct Scalars {
   int64_t obj;
   int64_t stats[SC_NSTATS];
   int32_t status;
-  int32_t nfront[2];
+  int32_t nfront[3];   // frontier sizes, by round mod 3
   int32_t nmoves;
   int32_t nrefill;
   int32_t pot_ok;   // pot is feasible for the current W
@@ -453,7 +453,9 @@ __device__ inline uint64_t lab_pack(int64_t dist, int32_t edges, int32_t pred) {
 // it so; with no negative cycle this least fixpoint does not depend on the
 // order of the relaxations, and it is reached in at most as many rounds as
 // synchronous rounds need, since every label is at least as good after each
-// round.  Two barriers per round: relax, then collect the next frontier.  A
+// round.  One barrier per round: a thread whose atomic minimum lowers a
+// label appends the center to the next frontier, unless the center's round
+// stamp (taken by atomic exchange) shows that another thread already has.  A
 // frontier entry holds the center and its row offset u*k; only the key's high
 // word of W (delta + 2^31, all ones = no edge) is read.  Returns false (and
 // sets the status) on a change in round k+1.
@@ -466,16 +468,17 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
   constexpr int WS = WLDS ? 2 : 1;
   const uint32_t *Whi = WLDS ? reinterpret_cast<const uint32_t *>(L.W) + 1 : L.wh;
   uint64_t *lab = L.red;                      // packed labels
-  int32_t *chg = L.hop;                       // changed in this round
+  int32_t *stamp = L.hop;                     // last round whose frontier took the center
   for (int v = tid; v <= k; v += NT) {
     lab[v] = (v == s) ? lab_pack(0, 0, 0) : KEY_NONE;
-    chg[v] = 0;
+    stamp[v] = 0;
   }
   if (tid == 0) {
-    S.nfront[0] = 1;
-    S.nfront[1] = 0;
-    L.front0[0] = s;
-    reinterpret_cast<int32_t *>(L.fbase0)[0] = s * k;
+    S.nfront[0] = 0;
+    S.nfront[1] = 1;
+    S.nfront[2] = 0;
+    L.front1[0] = s;
+    reinterpret_cast<int32_t *>(L.fbase1)[0] = s * k;
   }
   __syncthreads();
   // target v of this thread and its share g of the frontier (k <= NT: every
@@ -484,16 +487,24 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
   const int tv = k <= NT ? tid % k : tid;
   const int tg = k <= NT ? tid / k : 0;
   int64_t rounds = 0, relax = 0;
-  int cur = 0;
   bool conv = false;
   for (int t = 1; t <= k + 1; ++t) {
-    const int nf = S.nfront[cur];
-    const int32_t *F = cur ? L.front1 : L.front0;
-    const int32_t *FO = reinterpret_cast<const int32_t *>(cur ? L.fbase1 : L.fbase0);
+    // round t relaxes out of the frontier of size nfront[t % 3] in list t & 1,
+    // appends to nfront[(t + 1) % 3] and list (t + 1) & 1, and clears
+    // nfront[(t + 2) % 3]: that counter was last read before the previous
+    // barrier and is next appended to after the coming one
+    const int nf = S.nfront[t % 3];
+    const int32_t *F = (t & 1) ? L.front1 : L.front0;
+    const int32_t *FO = reinterpret_cast<const int32_t *>((t & 1) ? L.fbase1 : L.fbase0);
+    int32_t *Fn = (t & 1) ? L.front0 : L.front1;
+    int32_t *FOn = reinterpret_cast<int32_t *>((t & 1) ? L.fbase0 : L.fbase1);
+    int32_t *cnt_next = &S.nfront[(t + 1) % 3];
     // candidate of target v over frontier entries j = j0, j0+G, ... in
-    // batches of four: all loads of a batch are in flight together
+    // batches of four: all loads of a batch are in flight together.  Returns
+    // true when v's label dropped and v is not yet in the next frontier
+    // (several threads of a target may lower it; the stamp admits one).
     constexpr int B = 4;
-    auto relax_target = [&](int v, int j0) {
+    auto relax_target = [&](int v, int j0) -> bool {
       uint64_t best = KEY_NONE;
       for (int j = j0; j < nf; j += B * G) {
         int32_t u[B], off[B];
@@ -519,43 +530,38 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
                                   ((uint64_t)(int64_t)(int32_t)(hi[x] - 0x80000000u) << 22) +
                                   (1ull << 11) + (uint32_t)u[x]);
       }
-      if (best != KEY_NONE && best < atomicMin((unsigned long long *)&lab[v], (unsigned long long)best))
-        chg[v] = 1;
+      return best != KEY_NONE && best < atomicMin((unsigned long long *)&lab[v], (unsigned long long)best) &&
+             atomicExch(&stamp[v], t) != t;
     };
-    if (k <= NT) {
-      if (tg < G && tv != s) relax_target(tv, tg);
-    } else {
-      for (int v = tid; v < k; v += NT)
-        if (v != s) relax_target(v, 0);
-    }
-    __syncthreads();
-    int32_t *Fn = cur ? L.front0 : L.front1;
-    int32_t *FOn = reinterpret_cast<int32_t *>(cur ? L.fbase0 : L.fbase1);
-    for (int vb = 0; vb < k; vb += NT) {
-      const int v = vb + tid;
-      const bool ch = v < k && chg[v];
-      if (ch) chg[v] = 0;
-      // one LDS atomic per wavefront for the frontier append
-      const uint64_t mask = __ballot(ch);
+    // append the centers whose lanes say so: one LDS atomic per wavefront
+    auto append = [&](bool app, int v) {
+      const uint64_t mask = __ballot(app);
       if (mask) {
         int base = 0;
-        if ((tid & 63) == 0) base = atomicAdd(&S.nfront[cur ^ 1], __popcll(mask));
+        if ((tid & 63) == 0) base = atomicAdd(cnt_next, __popcll(mask));
         base = __builtin_amdgcn_readlane(base, 0);
-        if (ch) {
+        if (app) {
           Fn[base + lanes_below(mask)] = v;
           FOn[base + lanes_below(mask)] = v * k;
         }
       }
+    };
+    if (tid == 0) S.nfront[(t + 2) % 3] = 0;
+    if (k <= NT) {
+      append(tg < G && tv != s && relax_target(tv, tg), tv);
+    } else {
+      for (int vb = 0; vb < k; vb += NT) {
+        const int v = vb + tid;
+        append(v < k && v != s && relax_target(v, 0), v);
+      }
     }
     __syncthreads();
-    const int nnext = S.nfront[cur ^ 1];
+    const int nnext = *cnt_next;
     rounds += 1;
     relax += (int64_t)nf * k;
-    if (tid == 0) S.nfront[cur] = 0;
     if (nnext == 0) { conv = true; break; }
-    cur ^= 1;
   }
-  // unpack (chg is all zero again, and hop takes its place)
+  // unpack (hop takes the stamps' place)
   for (int v = tid; v < k; v += NT) {
     const uint64_t l = lab[v];
     const bool r = l != KEY_NONE;
@@ -960,6 +966,20 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
   __syncthreads();
   const bool ok0 = S.status == 0;
   int64_t r = r_begin;
+  // The last wavefront, which has no target of an allotment's joins while
+  // k <= NT - 64, fetches the cost-matrix row and the most suitable center
+  // of the unit PF_AHEAD iterations ahead into the caches: one word per 64
+  // bytes of the row (lane 63: the center).  The words are folded into a sink
+  // only PF_AHEAD iterations after their loads, so the allotments that follow
+  // do not wait for them, and the rows they read are then cache hits.
+  constexpr int PF_AHEAD = 2;
+  const bool pf_wave = k <= NT - 64 && tid >= NT - 64;
+  const int pf_lane = tid & 63;
+  int32_t pf_new = 0, pf_old = 0, pf_sink = 0;
+  // The allotment's bookkeeping (assignment, member list, load, objective)
+  // runs on a thread of a wavefront without join targets when there is one,
+  // so the joins do not wait behind its loads and stores.
+  const int t_book = k <= NT - 128 ? NT - 128 : 0;
   if (ok0) {
     for (; r < r_end; ++r) {
       // phase timers: thread 0, one iteration in 8 (a timer read holds up
@@ -968,15 +988,26 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
       const int64_t t0 = timed ? now() : 0;
       const int32_t *row = I.cm + r * k;
       int s = I.smin[r];
+      if (pf_wave) {
+        pf_sink += pf_old;
+        pf_old = pf_new;
+        pf_new = 0;
+        const int64_t rp = r + PF_AHEAD;
+        const int e = pf_lane * 16;
+        if (rp < I.n) {
+          if (pf_lane == 63) pf_new = I.smin[rp];
+          else if (e < k + 15) pf_new = I.cm[rp * k + min(e, k - 1)];
+        }
+      }
       if (I.strict) {
         // strict-LBDD: the cheapest center with free capacity (the most
         // suitable one whenever it has room); every thread reads the load
-        // before thread 0 changes it below
+        // before the bookkeeping thread changes it below
         const bool full = L.load[s] >= L.cap[s];
         __syncthreads();
         if (full) s = strict_center(I, L, S, row, s);
       }
-      if (tid == 0) {
+      if (tid == t_book) {
         const int ld = L.load[s];
         const int vac = ld < L.cap[s];
         S.vacant = vac;
@@ -1014,6 +1045,8 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
       if (S.status != 0) break;
     }
   }
+  pf_sink += pf_old + pf_new;
+  asm volatile("" : : "v"(pf_sink));          // keeps the fetches
   __syncthreads();
   if (WLDS)
     for (int64_t i = tid; i < (int64_t)k * k; i += NT) I.W[i] = L.W[i];
