@@ -59,10 +59,8 @@ struct Lds {
   int64_t *dist;    // [k+1]
   int32_t *pred;    // [k+1]
   int32_t *hop;     // [k+1] round in which the label last changed (0 for s)
-  int32_t *front0;  // [k+1] frontier lists (double-buffered) ...
+  int32_t *front0;  // [k+1] frontier lists (double-buffered)
   int32_t *front1;
-  uint64_t *fbase0; // [k+1] ... with their packed candidate bases
-  uint64_t *fbase1;
   int64_t *pot;     // [k] node potentials (see refine)
   int32_t *load;    // [k]
   int32_t *cap;     // [k]
@@ -101,7 +99,7 @@ struct Scalars {
 // without the k x k table in LDS.
 __host__ __device__ size_t solve_lds_bytes(int k, bool wlds) {
   const size_t K1 = (size_t)k + 1;
-  size_t b = K1 * 8 * 2 + K1 * 4 * 4 + 8 + K1 * 8 * 2 + (size_t)k * 8 + (size_t)k * 4 * 3 +
+  size_t b = K1 * 8 * 2 + K1 * 4 * 4 + 8 + (size_t)k * 8 + (size_t)k * 4 * 3 +
              K1 * 4 * 3 + K1 * 4 + 8 + 2 * (SOLVE_THREADS / 64) * 8;
   if (wlds) b += (size_t)k * k * 8;
   return b;
@@ -455,10 +453,9 @@ __device__ inline uint64_t lab_pack(int64_t dist, int32_t edges, int32_t pred) {
 // synchronous rounds need, since every label is at least as good after each
 // round.  One barrier per round: a thread whose atomic minimum lowers a
 // label appends the center to the next frontier, unless the center's round
-// stamp (taken by atomic exchange) shows that another thread already has.  A
-// frontier entry holds the center and its row offset u*k; only the key's high
-// word of W (delta + 2^31, all ones = no edge) is read.  Returns false (and
-// sets the status) on a change in round k+1.
+// stamp (taken by atomic exchange) shows that another thread already has.
+// Only the key's high word of W (delta + 2^31, all ones = no edge) is read.
+// Returns false (and sets the status) on a change in round k+1.
 template <bool WLDS>
 __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Scalars &S, int s) {
   const int k = I.k;
@@ -478,7 +475,6 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
     S.nfront[1] = 1;
     S.nfront[2] = 0;
     L.front1[0] = s;
-    reinterpret_cast<int32_t *>(L.fbase1)[0] = s * k;
   }
   __syncthreads();
   // target v of this thread and its share g of the frontier (k <= NT: every
@@ -495,9 +491,7 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
     // barrier and is next appended to after the coming one
     const int nf = S.nfront[t % 3];
     const int32_t *F = (t & 1) ? L.front1 : L.front0;
-    const int32_t *FO = reinterpret_cast<const int32_t *>((t & 1) ? L.fbase1 : L.fbase0);
     int32_t *Fn = (t & 1) ? L.front0 : L.front1;
-    int32_t *FOn = reinterpret_cast<int32_t *>((t & 1) ? L.fbase0 : L.fbase1);
     int32_t *cnt_next = &S.nfront[(t + 1) % 3];
     // candidate of target v over frontier entries j = j0, j0+G, ... in
     // batches of four: all loads of a batch are in flight together.  Returns
@@ -514,7 +508,7 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
           const int jj = j + x * G;
           ok[x] = jj < nf;
           u[x] = F[ok[x] ? jj : j];
-          off[x] = FO[ok[x] ? jj : j];
+          off[x] = u[x] * k;
         }
         uint64_t lu[B];
         uint32_t hi[B];
@@ -540,10 +534,7 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
         int base = 0;
         if ((tid & 63) == 0) base = atomicAdd(cnt_next, __popcll(mask));
         base = __builtin_amdgcn_readlane(base, 0);
-        if (app) {
-          Fn[base + lanes_below(mask)] = v;
-          FOn[base + lanes_below(mask)] = v * k;
-        }
+        if (app) Fn[base + lanes_below(mask)] = v;
       }
     };
     if (tid == 0) S.nfront[(t + 2) % 3] = 0;
@@ -922,8 +913,6 @@ __device__ __forceinline__ Lds carve_lds(const InstView &I, unsigned char *lds) 
   L.front0 = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
   L.front1 = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
   p = lds + (((p - lds) + 7) & ~(ptrdiff_t)7);   // offsets keep the LDS address space
-  L.fbase0 = reinterpret_cast<uint64_t *>(p); p += (size_t)K1 * 8;
-  L.fbase1 = reinterpret_cast<uint64_t *>(p); p += (size_t)K1 * 8;
   L.pot = reinterpret_cast<int64_t *>(p); p += (size_t)k * 8;
   L.load = reinterpret_cast<int32_t *>(p); p += (size_t)k * 4;
   L.cap = reinterpret_cast<int32_t *>(p); p += (size_t)k * 4;
