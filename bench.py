@@ -11,15 +11,18 @@ resident in HBM (a torch tensor) before timing starts.
 
 Prints one JSON line.  Extra objects:
   roofline      the solve kernel's cost-matrix bytes per second against HBM
-                peak, timed with HIP events on the stream it runs on
+                peak, timed with HIP events on the stream it runs on; the
+                solve is a chain of dependent iterations in one workgroup,
+                so its fraction is tiny by nature (limited_by says so)
   scan          the whole-matrix best-transfer scan at k=500, n=1,000,000
                 (2 GB of costs) against HBM peak
   tune          what the autotuner chose before timing: the search choice
-                for k=100 (timed on a solve prefix) and the scan's tiles
+                for k=100 (timed on whole solves) and the scan's tiles
   batch         batched launch vs plain solves on a subset of the batched
                 workload (solves/s, completion latency p50/p99)
   serve         request server vs plain FIFO on a Poisson trace (--serve N)
-  cpu_baseline  the CPU oracle timed on this host for one whole solve
+  cpu_baseline  the CPU oracle timed on this host for one whole solve, and
+                (para) its OpenMP build on every host thread
 """
 import argparse
 import json
@@ -366,7 +369,10 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": recorded_traffic("solve_kernel"),
                 "kernel": "solve_kernel", "bytes_per_launch": nbytes,
-                "launch_ms": round(kern_s * 1e3, 3)}
+                "launch_ms": round(kern_s * 1e3, 3),
+                "limited_by": "latency: one persistent workgroup runs the n dependent "
+                              "iterations (barriers, LDS and L2 round trips); the "
+                              "bandwidth-bound kernel is the scan (scan.kernel_frac)"}
 
     scan = None
     if not args.no_scan:
