@@ -21,6 +21,9 @@ Prints one JSON line.  Extra objects:
   batch         batched launch vs plain solves on a subset of the batched
                 workload (solves/s, completion latency p50/p99)
   serve         request server vs plain FIFO on a Poisson trace (--serve N)
+  strict        strict-LBDD (Appendix B) on the same instance
+  penalty_table the same instance with rising penalty tables (Section 2's
+                general penalty functions), objective against the oracle's
   cpu_baseline  the CPU oracle timed on this host for one whole solve, and
                 (para) its OpenMP build on every host thread
 """
@@ -278,6 +281,8 @@ def main():
                     help="skip the road-network workload (cost matrix on the GPU, then a solve)")
     ap.add_argument("--no-strict", action="store_true",
                     help="skip the strict-LBDD (Appendix B) solve of the same instance")
+    ap.add_argument("--no-table", action="store_true",
+                    help="skip the solve of the same instance with rising penalty tables")
     ap.add_argument("--cpu-batch", action="store_true",
                     help="also time the CPU oracle on the batched instances, one per host process")
     ap.add_argument("--no-tune", action="store_true",
@@ -308,7 +313,7 @@ def main():
     torch.cuda.synchronize()
     with open(os.path.join(ROOT, "tests", "golden", "oracle_results.json")) as f:
         golds = json.load(f)
-    gold, gold_strict = golds["C2"], golds["C2_strict"]
+    gold, gold_strict, gold_table = golds["C2"], golds["C2_strict"], golds["C2_table"]
 
     tune = {}
     if not args.no_tune:
@@ -492,6 +497,38 @@ def main():
                   "stats": sst}
         log(f"bench: strict solve {smean:.1f} ms, parity {strict['objective_matches_oracle']}")
 
+    table = None
+    if not args.no_table:
+        # general penalty functions (Section 2, Equation (2)): tables that start
+        # at the constant penalties and rise by U{0..20} per further unit
+        off, val = L.rising_penalties(inst, length=gold_table["table_length"],
+                                      seed=gold_table["table_seed"])
+
+        def table_step():
+            h = lbdd.Instance(cm, inst.cap, stream=stream, pen_table=(off, val))
+            ev0.record(stream)
+            h.solve()
+            ev1.record(stream)
+            o, st = h.objective(), h.stats()
+            h.close()
+            return o, st, ev0.elapsed_time(ev1)
+
+        log("bench: penalty-table solve of the same instance (warmup + timed)")
+        table_step()
+        tms, tobjs, tst = [], [], None
+        for _ in range(args.steps):
+            o, tst, ms = table_step()
+            tobjs.append(o)
+            tms.append(ms)
+        tmean = float(np.mean(tms))
+        table = {"workload": "the same k=100 n=100000 instance with penalty tables (2,000 values "
+                             "per center, rising by U{0..20} per further unit beyond capacity)",
+                 "solve_ms": round(tmean, 3), "solves_per_s": round(1e3 / tmean, 4),
+                 "objective": tobjs[-1],
+                 "objective_matches_oracle": all(o == gold_table["objective"] for o in tobjs),
+                 "stats": tst}
+        log(f"bench: penalty-table solve {tmean:.1f} ms, parity {table['objective_matches_oracle']}")
+
     road = None
     if not args.no_road:
         log("bench: road-network workload R1 (65,902 vertices, k=131, n=65,771)")
@@ -598,6 +635,7 @@ def main():
         "batch": batch,
         "serve": serve,
         "strict": strict,
+        "penalty_table": table,
         "road": road,
         "cpu_baseline": cpu,
     }

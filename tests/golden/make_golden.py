@@ -55,6 +55,21 @@ def main():
                             "bf_rounds", "heap_pushes", "iterations"], r.stats.tolist())),
             oracle_seconds=round(dt, 2))
         print(name + "_strict", r.objective, dt, flush=True)
+    # general penalty functions (the definition in Section 2, Equation (2)) on
+    # C2: tables that start at the constant penalties and rise by U{0..20} per
+    # further unit beyond capacity, 2,000 values per center
+    inst = L.make_config("C2")
+    off, val = L.rising_penalties(inst, length=2000, seed=2)
+    t = time.time()
+    r = oracle.solve_q(inst.cm, inst.cap, off, val)
+    dt = time.time() - t
+    res["C2_table"] = dict(
+        k=inst.k, n=inst.n, input_sha256=L.input_hash(inst), table_length=2000, table_seed=2,
+        objective=r.objective, assignment_sha256=assignment_hash(r.assign),
+        stats=dict(zip(["cycles", "paths", "moves", "cycle_searches", "path_searches",
+                        "bf_rounds", "heap_pushes", "iterations"], r.stats.tolist())),
+        oracle_seconds=round(dt, 2))
+    print("C2_table", r.objective, dt, flush=True)
     with open(OUT, "w") as f:
         json.dump(res, f, indent=1)
 
