@@ -1,0 +1,78 @@
+"""The solve kernel's node-potential checks, on the CPU against a check of
+every edge.
+
+Potentials certify that the best-transfer table has no negative cycle
+(Lemmas 1 and 2 keep it so between refinements), which lets the kernel skip
+searches exactly.  Two shortcuts decide whether a search's labels (distances
+from the anchor s over the centers) are feasible potentials:
+  * after a search that applied nothing, only the edges into s need checking:
+    the Bellman-Ford fixpoint satisfies every edge between other centers;
+  * after an applied refinement, only the rows of the centers it moved units
+    between, and the edges into s, need checking: no other entry changed.
+This test compares both shortcuts with the check of every edge."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import pins
+
+
+def _key(d):
+    return np.uint64(((int(d) + 2**31) << 32) | 5)
+
+
+def _table(rng, k, s):
+    pot = rng.integers(-6, 7, size=k)
+    W = np.full((k, k), pins.KEY_NONE, np.uint64)
+    for u in range(k):
+        for v in range(k):
+            # the anchor holds a unit, so it has an edge to every center
+            if u != v and (u == s or rng.random() < 0.7):
+                W[u, v] = _key(pot[v] - pot[u] + rng.integers(0, 3))
+    return W
+
+
+def feasible(W, p, rows=None, col=None):
+    """p[v] <= p[u] + W[u][v] on the edges of the given rows (all when None),
+    or on the given column alone."""
+    k = W.shape[0]
+    for u in range(k):
+        for v in range(k):
+            if u == v or W[u, v] == pins.KEY_NONE:
+                continue
+            if col is not None and v != col:
+                continue
+            if col is None and rows is not None and u not in rows:
+                continue
+            if p[v] > p[u] + pins.key_delta(W[u, v]):
+                return False
+    return True
+
+
+@pytest.mark.parametrize("seed", range(80))
+def test_labels_need_only_the_checked_edges(seed):
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(2, 10))
+    s = int(rng.integers(0, k))
+    W = _table(rng, k, s)
+    if rng.random() < 0.5:                      # sometimes a negative cycle through s
+        u = int(rng.integers(0, k))
+        if u != s:
+            W[u, s] = _key(pins.key_delta(W[s, u]) * -1 - int(rng.integers(1, 4)))
+    z = np.zeros(k, np.int32)
+    dist, _, _ = oracle.refine_search(W, s, 0, z, z, np.ones(k, np.int32))
+    p = [int(dist[v]) for v in range(k)]
+    # after a search that applied nothing: column s decides
+    assert feasible(W, p) == feasible(W, p, col=s), seed
+    # after an applied refinement: its centers' rows and column s decide
+    moved = {int(c) for c in rng.choice(k, size=int(rng.integers(1, k + 1)), replace=False)}
+    W2 = W.copy()
+    for u in moved:
+        for v in range(k):
+            if u != v and rng.random() < 0.6:
+                W2[u, v] = _key(int(rng.integers(-8, 9)))
+            elif u != v and rng.random() < 0.2:
+                W2[u, v] = pins.KEY_NONE
+    full = feasible(W2, p)
+    short = feasible(W2, p, rows=moved) and feasible(W2, p, col=s)
+    assert full == short, seed
