@@ -69,3 +69,30 @@ def test_s_in_label_from_the_center_labels(seed):
     h = min(hop[u] for u in mins)
     pred = min(u for u in mins if hop[u] == h)
     assert (dist_o[k], pred_o[k]) == (best, pred), seed
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_path_search_reuses_the_cycle_search_labels(seed):
+    """NCyc and NPath differ only in the edges into s*_in, so the center
+    labels of the two searches are the same and the path search's answer is
+    the rule above applied to the cycle search's labels."""
+    rng = np.random.default_rng(1000 + seed)
+    k = int(rng.integers(2, 10))
+    W = _table(rng, k)
+    s = int(rng.integers(0, k))
+    load = rng.integers(0, 4, size=k).astype(np.int32)
+    cap = rng.integers(0, 4, size=k).astype(np.int32)
+    pen = rng.integers(1, 12, size=k).astype(np.int32)
+    d0, p0, _ = oracle.refine_search(W, s, 0, load, cap, pen)
+    d1, p1, _ = oracle.refine_search(W, s, 1, load, cap, pen)
+    assert np.array_equal(d0[:k], d1[:k]) and np.array_equal(p0[:k], p1[:k])
+    E = pins.split_graph(W, s, 1, load, cap, pen)
+    dist, hop = center_labels(E, k, s)
+    into = {u: w for (u, v), w in E.items() if v == k and u in dist}
+    if not into:                                 # the anchor reaches no other center
+        assert d1[k] == oracle.DIST_NONE
+        return
+    best = min(dist[u] + w for u, w in into.items())
+    mins = [u for u, w in into.items() if dist[u] + w == best]
+    h = min(hop[u] for u in mins)
+    assert (d1[k], p1[k]) == (best, min(u for u in mins if hop[u] == h))
