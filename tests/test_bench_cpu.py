@@ -42,3 +42,14 @@ def test_recorded_traffic_is_null_for_changed_sources(tmp_path, monkeypatch):
         (tmp_path / src).write_bytes(open(os.path.join(ROOT, src), "rb").read())
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.recorded_traffic("solve_kernel") is None
+
+
+def test_stored_results_hold_what_the_bench_checks():
+    """Every objective bench.py compares against is stored, with the table
+    parameters the penalty-table step rebuilds its inputs from."""
+    with open(os.path.join(ROOT, "tests", "golden", "oracle_results.json")) as f:
+        gold = json.load(f)
+    for name in ("C2", "C2_strict", "C2_table"):
+        assert isinstance(gold[name]["objective"], int)
+    assert gold["C2_table"]["table_length"] > 0 and "table_seed" in gold["C2_table"]
+    assert gold["C2_table"]["input_sha256"] == gold["C2"]["input_sha256"]
