@@ -611,6 +611,15 @@ def main():
                 "sample": f"one whole strict solve of the same instance ({dts:.1f} s); objective "
                           f"{'matches' if rs.objective == gold_strict['objective'] else 'DIFFERS'}"}
             log(f"bench: strict oracle {dts:.1f} s")
+        if table is not None:
+            tc = time.perf_counter()
+            rt = oracle.solve_q(inst.cm, inst.cap, off, val)
+            dtt = time.perf_counter() - tc
+            table["cpu_baseline"] = {
+                "value": round(1.0 / dtt, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+                "sample": f"one whole solve of the same instance with the same tables ({dtt:.1f} s); "
+                          f"objective {'matches' if rt.objective == gold_table['objective'] else 'DIFFERS'}"}
+            log(f"bench: penalty-table oracle {dtt:.1f} s")
 
     out = {
         "metric": "cost-matrix GB/s (% HBM peak); LBDD solves/sec and p99 latency, batched vs plain",
