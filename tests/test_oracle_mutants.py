@@ -46,6 +46,10 @@ MUTANTS = {
     "strict_no_dummy_edges": ("if (S->strict && u != v", "if (0 && u != v"),
     "strict_allot_ignores_capacity": ("if (S.load[t] < capx[t] && (s < 0", "if ((s < 0"),
     "strict_dummy_cost_not_above_max": ("cmx[d * kx + k] = maxcm + 1;", "cmx[d * kx + k] = maxcm;"),
+    "objective_penalty_on_whole_load": ("total += (int64_t)pen[s] * (load[s] - cap[s]);",
+                                        "total += (int64_t)pen[s] * load[s];"),
+    "objective_counts_unallotted": ("        if (s < 0) continue;\n        if (s >= k) { free(load); return ORC_E_INVAL; }",
+                                    "        if (s < 0) s = 0;\n        if (s >= k) { free(load); return ORC_E_INVAL; }"),
 }
 
 
@@ -144,7 +148,19 @@ def _pin_failures(lib):
                 return False
         return True
 
-    for name, fn in [("setup", setup_ok), ("hand_trace", hand_trace_ok), ("search", search_ok),
+    def objective_ok():
+        for s in range(6):
+            rng = np.random.default_rng(40 + s)
+            k, n = 2 + s % 4, 60
+            cm = rng.integers(0, 100, size=(n, k)).astype(np.int32)
+            cap = rng.integers(0, n // k, size=k).astype(np.int32)
+            pen = rng.integers(1, 50, size=k).astype(np.int32)
+            a = rng.integers(-1, k, size=n).astype(np.int32)
+            if oracle.objective(cm, cap, pen, a, lib=lib) != pins.eq1(cm, cap, pen, a):
+                return False
+        return True
+
+    for name, fn in [("setup", setup_ok), ("objective", objective_ok), ("hand_trace", hand_trace_ok), ("search", search_ok),
                      ("solve", solve_ok), ("zero_cap", zero_cap_ok), ("strict", strict_ok),
                      ("table", table_ok), ("road", road_ok)]:
         check(name, fn)

@@ -242,3 +242,48 @@ def test_invalid_inputs_rejected(orc):
         with pytest.raises(orc.OracleError) as e:
             orc.solve(*bad)
         assert e.value.rc == orc.E_INVAL
+
+
+# ------------------------------------------------------ Equation (1) itself
+def test_objective_hand_example(orc):
+    """Equation (1) worked by hand: units 0 and 1 at center 0 (capacity 1, so
+    one unit beyond it pays 10), unit 2 not allotted, unit 3 at center 1 within
+    capacity: 1 + 2 + 10 + 6 = 19."""
+    cm = np.array([[1, 5], [2, 3], [4, 0], [9, 6]], np.int32)
+    cap = np.array([1, 1], np.int32)
+    pen = np.array([10, 7], np.int32)
+    assert orc.objective(cm, cap, pen, np.array([0, 0, -1, 1], np.int32)) == 19
+    # every unit at center 1: 5 + 3 + 0 + 6 plus three units beyond capacity at 7
+    assert orc.objective(cm, cap, pen, np.array([1, 1, 1, 1], np.int32)) == 14 + 21
+    # nothing allotted
+    assert orc.objective(cm, cap, pen, np.full(4, -1, np.int32)) == 0
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_objective_matches_equation_1(orc, seed):
+    """Random allotments with unallotted units, overloaded, empty and
+    zero-capacity centers against the independent rendering of Equation (1)."""
+    rng = np.random.default_rng(seed)
+    k, n = int(rng.integers(1, 12)), int(rng.integers(1, 400))
+    cm = rng.integers(0, 1 << 20, size=(n, k)).astype(np.int32)
+    cap = rng.integers(0, max(2, n // k), size=k).astype(np.int32)
+    pen = rng.integers(1, 1 << 20, size=k).astype(np.int32)
+    assign = rng.integers(-1, k, size=n).astype(np.int32)
+    load = np.bincount(assign[assign >= 0], minlength=k)
+    if seed % 2 == 0:
+        assert (load > cap).any()                # some center pays penalties
+    assert orc.objective(cm, cap, pen, assign) == pins.eq1(cm, cap, pen, assign)
+
+
+def test_objective_of_a_solve_equals_its_tracked_delta(orc):
+    """The objective ASRAL tracks step by step equals Equation (1) evaluated
+    on the allotment it returns."""
+    inst = L.make_config("C1")
+    r = orc.solve(*inst.arrays())
+    assert orc.objective(*inst.arrays(), r.assign) == r.objective == pins.eq1(*inst.arrays(), r.assign)
+
+
+def test_objective_rejects_unknown_center(orc):
+    cm = np.ones((3, 2), np.int32)
+    with pytest.raises(orc.OracleError):
+        orc.objective(cm, np.ones(2, np.int32), np.ones(2, np.int32), np.array([0, 2, 1], np.int32))
