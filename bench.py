@@ -323,7 +323,7 @@ def main():
         log(f"bench: search autotuner, {titers} iterations per candidate")
         ratio, cand_ms = lbdd.tune_search(cm, inst.cap, inst.pen, iters=titers, stream=stream)
         tune["search"] = {"k": inst.k, "iters_per_candidate": titers, "chosen_ratio_x16": ratio,
-                          "candidates_ratio_x16": [0, 32, 64, 128, 1 << 20],
+                          "candidates_ratio_x16": list(lbdd.SEARCH_CANDIDATES),
                           "candidates_ms": [round(x, 3) for x in cand_ms]}
         log(f"bench: search autotuner chose ratio {ratio} ({cand_ms} ms)")
 

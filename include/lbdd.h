@@ -205,20 +205,31 @@ int lbdd_snapshot(lbdd_instance *h, int32_t *load, uint64_t *W, int64_t *order);
  *        on the same table (part of [4])
  *   [18] searches run in Dijkstra order on feasible node potentials (part
  *        of [3] + [4]; the others run as Bellman-Ford rounds or are [17])
- *   [19] applied refinements after which the search labels were still
- *        feasible node potentials of the changed table
- *   [20] device timer frequency in kHz
+ *   [19] applied refinements after which the node potentials were kept
+ *        (the search's candidate potentials, repaired where needed)
+ *   [20] centers settled by the searches of [18] (each stops once no open
+ *        center can lower the s_in label below 0 or below the best found)
+ *   [21] candidate potentials repaired (shortest distances on reduced
+ *        weights from the tails of the edges that failed the check)
+ *   [22] rounds of those repairs
+ *   [23] .. [25] device timer ticks spent in searches in Dijkstra order, in
+ *        Bellman-Ford searches, and in potential checks and repairs
+ *   [26] device timer frequency in kHz
  * Synchronises.  Returns the number of counters written (>= 0). */
 int lbdd_stats(lbdd_instance *h, int64_t *out, int32_t count);
 
 /* Per-instance options (none changes a result, only how fast it comes).
- *   LBDD_OPT_SEARCH_RATIO  int64 in [0, 2^20]: the cost of one Bellman-Ford
+ *   LBDD_OPT_SEARCH_RATIO  int64 in [-1, 2^20]: the cost of one Bellman-Ford
  *     round in Dijkstra steps, x16.  A refinement search runs in Dijkstra
- *     order (when the node potentials allow it and k <= 192 with the table in
- *     LDS) if the running mean of the rounds a search needs, times the ratio,
- *     exceeds k.  0: always Bellman-Ford; 2^20: Dijkstra whenever allowed.
- *     New instances start with the value lbdd_tune_search recorded for their
- *     k in this process, else 64.
+ *     order (when the node potentials allow it and k <= 512) if the running
+ *     mean of the rounds a Bellman-Ford search needs, times the ratio,
+ *     exceeds the running mean of the centers a search in Dijkstra order
+ *     settles (both means kept per search mode).  -1: the ratio is measured
+ *     during the solve from the device times of rounds and steps (one search
+ *     in 64 takes the other kind to keep both times current); 0: always
+ *     Bellman-Ford; 2^20: Dijkstra whenever allowed.  New instances start
+ *     with the value lbdd_tune_search recorded for their k in this process,
+ *     else -1.
  * lbdd_set_option takes effect at the next solve launch.  Both synchronise
  * the instance's stream.  Errors: LBDD_E_INVAL (NULL, unknown option, value
  * out of range), LBDD_E_DEVICE. */
@@ -356,15 +367,15 @@ int lbdd_best_transfers_batch(int32_t m, const int32_t *k, const int64_t *n, con
  * configuration up when it is launched.
  *
  * lbdd_tune_search: creates a fresh instance from the inputs (arguments as
- * lbdd_create) once per candidate search ratio (0, 32, 64, 128, 2^20), times
- * its first `iters` iterations with HIP events on `hip_stream`, checks that
- * all candidates reach the same objective, and records the fastest ratio for
- * this k (used by later lbdd_create calls) if it beats the default (64) by
+ * lbdd_create) once per candidate search ratio (-1, 0, 64, 2^20), times its
+ * first `iters` iterations with HIP events on `hip_stream`, checks that all
+ * candidates reach the same objective, and records the fastest ratio for
+ * this k (used by later lbdd_create calls) if it beats the default (-1) by
  * more than 2 %, else the default.  A short prefix has few searches: time
- * enough iterations (up to n) to tell the candidates apart.  Writes it to *ratio_out and the
- * candidates' times in ms to ms_out[0 .. count-1].  Synchronises.  Returns
- * the number of candidates (5), or LBDD_E_INVAL, LBDD_E_NOMEM, LBDD_E_DEVICE,
- * LBDD_E_INTERNAL (candidates disagreed). */
+ * enough iterations (up to n) to tell the candidates apart.  Writes it to
+ * *ratio_out and the candidates' times in ms to ms_out[0 .. count-1].
+ * Synchronises.  Returns the number of candidates (4), or LBDD_E_INVAL,
+ * LBDD_E_NOMEM, LBDD_E_DEVICE, LBDD_E_INTERNAL (candidates disagreed). */
 int lbdd_tune_search(int32_t k, int64_t n, const int32_t *cm, const int32_t *capacity,
                      const int32_t *penalty, uint32_t flags, int64_t iters, void *hip_stream,
                      int64_t *ratio_out, float *ms_out, int32_t count);

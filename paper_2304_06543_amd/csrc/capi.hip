@@ -282,8 +282,8 @@ int lbdd_centers(lbdd_instance *h, int32_t *k_graph) {
 int lbdd_set_option(lbdd_instance *h, int32_t option, int64_t value) {
   if (!h) return fail(LBDD_E_INVAL, "NULL handle");
   if (option != LBDD_OPT_SEARCH_RATIO) return fail(LBDD_E_INVAL, "unknown option %d", option);
-  if (value < 0 || value > lbdd::MAX_SEARCH_RATIO)
-    return fail(LBDD_E_INVAL, "search ratio %lld outside [0, 2^20]", (long long)value);
+  if (value < lbdd::SEARCH_RATIO_AUTO || value > lbdd::MAX_SEARCH_RATIO)
+    return fail(LBDD_E_INVAL, "search ratio %lld outside [-1, 2^20]", (long long)value);
   HIP_TRY(copy_sync(h->scalars + lbdd::SC_RATIO, &value, sizeof value, hipMemcpyHostToDevice, h->st),
           "set option");
   return LBDD_OK;

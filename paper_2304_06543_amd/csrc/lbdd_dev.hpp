@@ -79,12 +79,14 @@ enum : int {
   SC_DONE = 1,          // iterations completed
   SC_STATUS = 2,        // 0 ok, else an LBDD_E_* code
   SC_STAT0 = 3,         // first of the counters reported by lbdd_stats
-  SC_NSTATS = 20,
+  SC_NSTATS = 26,
   SC_RATIO = SC_STAT0 + SC_NSTATS,   // search-choice ratio (x16, see refine in solve.hip)
   SC_COUNT = SC_RATIO + 1
 };
-// A Bellman-Ford round costs about this many (x16) Dijkstra steps unless tuned.
-constexpr int64_t DEFAULT_SEARCH_RATIO = 64;
+// Cost of a Bellman-Ford round in Dijkstra steps (x16), or AUTO: the ratio
+// of the measured times of a round and of a step (the default unless tuned).
+constexpr int64_t SEARCH_RATIO_AUTO = -1;
+constexpr int64_t DEFAULT_SEARCH_RATIO = SEARCH_RATIO_AUTO;
 constexpr int64_t MAX_SEARCH_RATIO = 1 << 20;   // Dijkstra whenever it applies
 enum : int {
   ST_CYCLES = 0, ST_PATHS, ST_MOVES, ST_CYC_SEARCH, ST_PATH_SEARCH, ST_BF_ROUNDS,
@@ -97,7 +99,13 @@ enum : int {
   ST_RELAX,             // Bellman-Ford edge relaxations (frontier size x targets)
   ST_PATH_DERIVED,      // path searches answered from the cycle search's labels
   ST_DIJKSTRA,          // searches run in Dijkstra order on feasible potentials
-  ST_POT_KEPT           // applied refinements whose labels stayed feasible potentials
+  ST_POT_KEPT,          // applied refinements whose labels stayed feasible potentials
+  ST_DJ_SETTLED,        // centers settled by searches in Dijkstra order
+  ST_POT_REPAIRS,       // candidate potentials repaired after a failed check
+  ST_REPAIR_ROUNDS,     // rounds of those repairs
+  // device timer ticks spent in (thread 0's view): searches in Dijkstra
+  // order, Bellman-Ford searches, potential checks and repairs
+  ST_T_DIJKSTRA, ST_T_BF, ST_T_POT
 };
 
 // one workgroup solves one instance

@@ -148,10 +148,13 @@ void lbdd_server::loop() {
       std::vector<int32_t> a((size_t)j.n);
       int rc = lbdd_objective(inst, &obj);
       if (rc == LBDD_OK) rc = lbdd_assignment(inst, a.data(), 0);
-      int64_t st[21] = {0};
-      if (rc == LBDD_OK && lbdd_stats(inst, st, 21) == 21 && st[20] > 0) {
-        j.t_dev0 = (double)st[14] / ((double)st[20] * 1e3);
-        j.t_dev1 = (double)st[15] / ((double)st[20] * 1e3);
+      // the counters of lbdd_stats, then the device timer's rate (kHz)
+      constexpr int NST = lbdd::SC_NSTATS + 1;
+      int64_t st[NST] = {0};
+      if (rc == LBDD_OK && lbdd_stats(inst, st, NST) == NST && st[lbdd::SC_NSTATS] > 0) {
+        const double hz = (double)st[lbdd::SC_NSTATS] * 1e3;
+        j.t_dev0 = (double)st[lbdd::ST_T_FIRST] / hz;
+        j.t_dev1 = (double)st[lbdd::ST_T_LAST] / hz;
       }
       lbdd_destroy(inst);
       lk.lock();

@@ -62,6 +62,7 @@ struct Lds {
   int32_t *front0;  // [k+1] frontier lists (double-buffered)
   int32_t *front1;
   int64_t *pot;     // [k] node potentials (see refine)
+  int64_t *pot2;    // [k] candidate potentials from the last search
   int32_t *load;    // [k]
   int32_t *cap;     // [k]
   int32_t *pen;     // [k]
@@ -87,9 +88,14 @@ struct Scalars {
   int32_t nrefill;
   int32_t pot_ok;   // pot is feasible for the current W
   int32_t vacant;
-  int32_t ratio;    // cost of a Bellman-Ford round in Dijkstra steps, x16
-  int32_t depth;    // running mean of (deepest hop + 1) of recent searches, x16
-  int32_t maxhop;   // deepest hop of the last search in Dijkstra order
+  int32_t ratio;    // cost of a Bellman-Ford round in Dijkstra steps, x16, or
+                    // SEARCH_RATIO_AUTO: measured (round_t / step_t)
+  int32_t depth[2];    // running means, per search mode, of the rounds of
+                       // Bellman-Ford searches and of the centers settled by
+  int32_t settled[2];  // searches in Dijkstra order, x16
+  int32_t round_t;  // running mean of the device ticks per Bellman-Ford round, x16
+  int32_t step_t;   // running mean of the device ticks per Dijkstra step, x16
+  int32_t nsearch;  // searches run (Bellman-Ford or Dijkstra order)
   int32_t jflags[2];  // join_center's result, by iteration parity
 };
 
@@ -99,7 +105,7 @@ struct Scalars {
 // without the k x k table in LDS.
 __host__ __device__ size_t solve_lds_bytes(int k, bool wlds) {
   const size_t K1 = (size_t)k + 1;
-  size_t b = K1 * 8 * 2 + K1 * 4 * 4 + 8 + (size_t)k * 8 + (size_t)k * 4 * 3 +
+  size_t b = K1 * 8 * 2 + K1 * 4 * 4 + 8 + (size_t)k * 8 * 2 + (size_t)k * 4 * 3 +
              K1 * 4 * 3 + K1 * 4 + 8 + 2 * (SOLVE_THREADS / 64) * 8;
   if (wlds) b += (size_t)k * k * 8;
   return b;
@@ -368,54 +374,121 @@ __device__ __forceinline__ void refill_moved(const InstView &I, const Lds &L, Sc
   }
 }
 
-// After a search that applied nothing the labels are a feasible potential:
-// dist[v] <= dist[u] + W[u][v] holds for edges between centers by the
-// Bellman-Ford fixpoint (every center is reachable: the anchor holds at
-// least one unit, so it has an edge to every other center), and the edges
-// into the anchor need 0 <= dist[u] + W[u][s], i.e. no negative cycle through
-// s, which is checked here rather than assumed.
-__device__ __forceinline__ void adopt_potential(const InstView &I, const Lds &L, Scalars &S, int s) {
+// Potentials certify that W has no negative cycle, which lets searches be
+// skipped or run in Dijkstra order.  A search leaves candidate potentials in
+// pot2 (Bellman-Ford: the labels, i.e. distances from s; Dijkstra order: the
+// labels of the settled centers and shifted old potentials for the others,
+// see dijkstra_bounded), feasible (pot2[v] <= pot2[u] + W[u][v]) on every
+// edge of the searched table except possibly those out of s and into s.
+// An applied refinement then changed only the rows of the centers it moved
+// units between.  So checking those rows, row s and column s decides
+// feasibility on the whole current table.  nmov = 0 after a search that
+// applied nothing.
+//
+// Where some checked edges fail, pot2 is repaired rather than dropped: W has
+// no negative cycle (Lemmas 1 and 2), so the shortest distances lab(v) <= 0
+// from a virtual source joined to every center by a 0-weight edge, on the
+// reduced weights W[u][v] + pot2[u] - pot2[v], exist, and pot2 + lab is
+// feasible on every edge.  Only a failed edge has a negative reduced weight,
+// so with every label starting at 0 only the tails of failed edges can lower
+// a label in the first round; later rounds relax out of the centers whose
+// label dropped (rounds as in bellman_ford, on plain int64 labels).  The
+// result is shifted so that the potential of s is 0: every center with units
+// has edges to and from s, so its potential stays within 2^30 of 0.
+constexpr int64_t REP_BIAS = 1ll << 62;   // repair labels lie in (-2^62, 0]
+// Floor of a candidate potential.  Only a center without out-edges (no
+// units) can sink this low (one with an edge into s stays within 2^30 of it); raising such a center's potential keeps its in-edges feasible, whose
+// sources have out-edges and so potentials far above the floor.
+constexpr int64_t POT_FLOOR = -(1ll << 42);
+template <bool WLDS>
+__device__ __forceinline__ void take_potential(const InstView &I, const Lds &L, Scalars &S, int s,
+                                               int nmov) {
   const int k = I.k;
-  int bad = 0;
-  for (int u = threadIdx.x; u < k; u += NT) {
-    if (u == s) continue;
-    if (L.dist[u] == DIST_NONE) { bad = 1; continue; }
-    const uint64_t key = L.W[(int64_t)u * k + s];
-    if (key != KEY_NONE && L.dist[u] + key_delta(key) < 0) bad = 1;
+  const int tid = threadIdx.x;
+  // high word of W[i]: Whi[WS * i]
+  constexpr int WS = WLDS ? 2 : 1;
+  const uint32_t *Whi = WLDS ? reinterpret_cast<const uint32_t *>(L.W) + 1 : L.wh;
+  // repair labels (biased) and round stamps; the search labels (dist, hop,
+  // pred) stay intact for a path search derived from them
+  uint64_t *lab = L.red;
+  int32_t *stamp = L.trow;                       // last round whose frontier took the center
+  const int64_t t_start = tid == 0 ? now() : 0;
+  int unknown = 0;
+  for (int u = tid; u < k; u += NT) {
+    unknown |= L.pot2[u] == DIST_NONE;
+    lab[u] = (uint64_t)REP_BIAS;
+    stamp[u] = 0;
   }
-  bad = __syncthreads_or(bad);
-  if (!bad)
-    for (int u = threadIdx.x; u < k; u += NT) L.pot[u] = (u == s) ? 0 : L.dist[u];
-  if (threadIdx.x == 0) S.pot_ok = !bad;
+  if (tid == 0) { S.nfront[0] = S.nfront[1] = S.nfront[2] = 0; }
   __syncthreads();
-}
-
-// After a refinement has been applied, its labels (shortest distances from s
-// on the table before the moves) are tried as the node potentials of the new
-// table.  The moves change only the rows of the centers they move units
-// between, and the labels satisfy every other edge except those into s (the
-// search never enters s), so checking those rows and column s decides
-// feasibility exactly.
-__device__ __forceinline__ void retry_potential(const InstView &I, const Lds &L, Scalars &S, int s,
-                                                int nmov) {
-  const int k = I.k;
-  int bad = 0;
-  for (int u = threadIdx.x; u < k; u += NT) bad |= L.dist[u] == DIST_NONE;
-  const int nrows = 2 * nmov + 1;                // from/to of every move, then column s
-  for (int64_t t = threadIdx.x; t < (int64_t)nrows * k; t += NT) {
-    const int j = (int)(t / k), w = (int)(t - (int64_t)j * k);
-    const int u = j < 2 * nmov ? ((j & 1) ? L.mto[j >> 1] : L.mfrom[j >> 1]) : w;
-    const int v = j < 2 * nmov ? w : s;
-    if (u == v || L.dist[u] == DIST_NONE || L.dist[v] == DIST_NONE) continue;
-    const uint64_t key = L.W[(int64_t)u * k + v];
-    if (key != KEY_NONE && L.dist[u] + key_delta(key) < L.dist[v]) bad = 1;
+  // the check; the tails of failed edges form the first frontier (list 1)
+  const int nrows = 2 * nmov + 2;                // from/to of every move, row s, column s
+  if (!unknown)
+    for (int64_t t = tid; t < (int64_t)nrows * k; t += NT) {
+      const int j = (int)(t / k), w = (int)(t - (int64_t)j * k);
+      int u, v;
+      if (j < 2 * nmov) { u = (j & 1) ? L.mto[j >> 1] : L.mfrom[j >> 1]; v = w; }
+      else if (j == 2 * nmov) { u = s; v = w; }
+      else { u = w; v = s; }
+      if (u == v) continue;
+      const uint32_t hi = Whi[WS * ((int64_t)u * k + v)];
+      if (hi == 0xffffffffu) continue;
+      const int64_t d = (int64_t)(int32_t)(hi ^ 0x80000000u);
+      if (L.pot2[u] + d < L.pot2[v] && atomicExch(&stamp[u], 1) != 1)
+        L.front1[atomicAdd(&S.nfront[1], 1)] = u;
+    }
+  unknown = __syncthreads_or(unknown);
+  bool ok = !unknown;
+  const int nbad = S.nfront[1];
+  if (ok && nbad > 0) {
+    // repair rounds: round t relaxes out of the frontier of size nfront[t % 3]
+    // in list t & 1 (see bellman_ford)
+    bool conv = false;
+    int64_t rounds = 0;
+    for (int t = 1; t <= k + 1; ++t) {
+      const int nf = S.nfront[t % 3];
+      const int32_t *F = (t & 1) ? L.front1 : L.front0;
+      int32_t *Fn = (t & 1) ? L.front0 : L.front1;
+      int32_t *cnt_next = &S.nfront[(t + 1) % 3];
+      if (tid == 0) S.nfront[(t + 2) % 3] = 0;
+      for (int64_t x = tid; x < (int64_t)nf * k; x += NT) {
+        const int j = (int)(x / k), v = (int)(x - (int64_t)j * k);
+        const int u = F[j];
+        if (u == v) continue;
+        const uint32_t hi = Whi[WS * ((int64_t)u * k + v)];
+        if (hi == 0xffffffffu) continue;
+        const int64_t cand = (int64_t)(lab[u] - (uint64_t)REP_BIAS) + (int64_t)(int32_t)(hi ^ 0x80000000u) +
+                             L.pot2[u] - L.pot2[v];
+        if (cand >= 0) continue;
+        const uint64_t c = (uint64_t)(cand + REP_BIAS);
+        if (c < atomicMin((unsigned long long *)&lab[v], (unsigned long long)c) &&
+            atomicExch(&stamp[v], t + 1) != t + 1)
+          Fn[atomicAdd(cnt_next, 1)] = v;
+      }
+      __syncthreads();
+      ++rounds;
+      if (*cnt_next == 0) { conv = true; break; }
+    }
+    ok = conv;
+    if (ok) {
+      const int64_t shift = L.pot2[s] + (int64_t)(lab[s] - (uint64_t)REP_BIAS);
+      for (int u = tid; u < k; u += NT) {
+        const int64_t p = L.pot2[u] + (int64_t)(lab[u] - (uint64_t)REP_BIAS) - shift;
+        L.pot2[u] = p < POT_FLOOR ? POT_FLOOR : p;
+      }
+    }
+    if (tid == 0) {
+      S.stats[ST_POT_REPAIRS] += 1;
+      S.stats[ST_REPAIR_ROUNDS] += rounds;
+    }
   }
-  bad = __syncthreads_or(bad);
-  if (!bad)
-    for (int u = threadIdx.x; u < k; u += NT) L.pot[u] = L.dist[u];
-  if (threadIdx.x == 0) {
-    S.pot_ok = !bad;
-    if (!bad) S.stats[ST_POT_KEPT] += 1;
+  __syncthreads();
+  if (ok)
+    for (int u = tid; u < k; u += NT) L.pot[u] = L.pot2[u];
+  if (tid == 0) {
+    S.pot_ok = ok;
+    if (ok && nmov > 0) S.stats[ST_POT_KEPT] += 1;
+    S.stats[ST_T_POT] += now() - t_start;
   }
   __syncthreads();
 }
@@ -457,9 +530,10 @@ __device__ inline uint64_t lab_pack(int64_t dist, int32_t edges, int32_t pred) {
 // Only the key's high word of W (delta + 2^31, all ones = no edge) is read.
 // Returns false (and sets the status) on a change in round k+1.
 template <bool WLDS>
-__device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Scalars &S, int s) {
+__device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Scalars &S, int s, int mode) {
   const int k = I.k;
   const int tid = threadIdx.x;
+  const int64_t t_start = tid == 0 ? now() : 0;
   // high word of W[i]: Whi[WS * i] (in the LDS copy of W, or the packed
   // global array next to the global W)
   constexpr int WS = WLDS ? 2 : 1;
@@ -557,13 +631,19 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
     const uint64_t l = lab[v];
     const bool r = l != KEY_NONE;
     L.dist[v] = r ? (int64_t)(l >> 22) - LAB_BIAS : DIST_NONE;
+    L.pot2[v] = L.dist[v];
     L.hop[v] = r ? (int32_t)((l >> 11) & 0x7ff) : -1;
     L.pred[v] = (r && v != s) ? (int32_t)(l & 0x7ff) : -1;
   }
   if (tid == 0) {
     S.stats[ST_BF_ROUNDS] += rounds;
     S.stats[ST_RELAX] += relax;
-    S.depth += ((int32_t)rounds * 16 - S.depth) / 8;
+    S.depth[mode] += ((int32_t)rounds * 16 - S.depth[mode]) / 8;
+    const int64_t spent = now() - t_start;
+    S.stats[ST_T_BF] += spent;
+    const int64_t per = spent * 16 / (rounds > 0 ? rounds : 1);
+    S.round_t += ((int32_t)min(per, (int64_t)INT32_MAX / 2) - S.round_t) / 8;
+    S.nsearch += 1;
     if (!conv) S.status = -5;   // LBDD_E_INTERNAL: negative cycle reachable
   }
   __syncthreads();
@@ -667,42 +747,95 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
 // search never enters s, so only its first hops can have negative reduced
 // weight w(u, v) + pot[u] - pot[v]).  Centers are settled in the order of
 // (reduced label, edges), which is a valid Dijkstra order for these pairs of
-// weights, so each center ends with its shortest distance and the fewest
+// weights, so each settled center has its shortest distance and the fewest
 // edges among its shortest paths: the label and the round in which the
-// synchronous Bellman-Ford rounds fix it.  The predecessor is the smallest
-// settled center that reaches v with that pair (the smallest candidate of
-// that round).  Center v belongs to lane v % 64, slot v / 64; s_in follows
-// from the center labels.
-constexpr int64_t DJ_BIAS = 1ll << 45;   // reduced labels stay within +-2^44
-constexpr int DJ_MAX_NPL = 3;            // centers per lane (k <= 192)
-template <int NPL>
-__device__ __forceinline__ void dijkstra_wave(const InstView &I, const Lds &L, Scalars &S, int s) {
+// synchronous Bellman-Ford rounds fix it.  Its predecessor is the smallest
+// settled center that reaches it with that pair (the smallest candidate of
+// that round).  Center v belongs to lane v % 64, slot v / 64.
+//
+// The search stops as soon as no open center can matter for s_in, whose
+// candidate through u is u's label + w(u, s_in):
+//   cycle mode: w(u, s) is feasible, so the candidate is at least u's reduced
+//     label; after s, centers are settled while the smallest open reduced
+//     label is negative;
+//   path mode: the candidate is u's reduced label + P(u), P(u) = pot[u] +
+//     w(u, s_in) - pot[s]; the search stops once (smallest open reduced
+//     label) + min P exceeds both -1 and the best candidate so far.
+// Every center that attains s_in's label, if it is negative, is settled, so
+// sin_from_labels gives the synchronous rounds' s_in label and path.  Open
+// centers get DIST_NONE.  The candidate potentials pot2 are the labels of the
+// settled centers and pot[v] - pot[s] + D for the others, D >= 0 the reduced
+// label the search stopped at: with D no smaller than any settled reduced
+// label and no open center below it, pot2 is feasible on every edge that pot
+// was, and on the edges out of s as well.
+// Key of an open center: ((reduced label + DJ_BIAS) << 18) | (edges << 9) |
+// predecessor, so one unsigned minimum orders by (reduced label, edges) and
+// keeps the smallest predecessor among equal pairs.  Reduced labels stay
+// within +-2^44 (|potential| <= 2^42, |distance| < k * 2^30 <= 2^39) and
+// edges and centers below 512.
+constexpr int64_t DJ_BIAS = 1ll << 45;
+constexpr int DJ_SHIFT = 18;
+template <bool WLDS, int NPL>
+__device__ __forceinline__ void dijkstra_bounded(const InstView &I, const Lds &L, Scalars &S, int s,
+                                                 int mode) {
   const int k = I.k;
   if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    const uint32_t *Whi = reinterpret_cast<const uint32_t *>(L.W) + 1;
-    // open: tentative key ((reduced label + DJ_BIAS) << 12 | edges) of an
-    // unsettled center, all ones once settled or while unreached; fin: the
-    // key a center was settled with
-    uint64_t open[NPL], fin[NPL];
-    int32_t pred[NPL];
-    int64_t pv[NPL];
-    bool done[NPL];
+    // an opaque copy of the lane index: what derives from it is computed here
+    // rather than hoisted to the kernel's start, where it would hold
+    // registers for the whole solve
+    int lane = threadIdx.x;
+    asm volatile("" : "+v"(lane));
+    // high word of W[i]: Whi[WS * i]
+    constexpr int WS = WLDS ? 2 : 1;
+    const uint32_t *Whi = WLDS ? reinterpret_cast<const uint32_t *>(L.W) + 1 : L.wh;
+    const int64_t t_start = now();
+    const int64_t pot_s = L.pot[s];
+    // path mode: what the anchor saves per unit it gives up; the bound term
+    // P(u) = pot[u] + w(u, s_in) - pot[s] of a center u != s
+    const int64_t q_anchor =
+        mode == 0 ? 0 : penalty_at(I, L, s, L.load[s] > L.cap[s] ? (int64_t)L.load[s] - L.cap[s] : 1);
+    auto bound_term = [&](int u) -> int64_t {
+      const int64_t w =
+          (L.load[u] >= L.cap[u] ? penalty_at(I, L, u, (int64_t)L.load[u] - L.cap[u] + 1) : 0) - q_anchor;
+      return L.pot[u] + w - pot_s;
+    };
+    // open key of an unsettled center, all ones once settled or while
+    // unreached
+    uint64_t open[NPL];
+    uint32_t done = 0;                           // bit i: slot i settled or beyond k
+    uint64_t pm = KEY_NONE;
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
       const int v = lane + 64 * i;
-      pv[i] = v < k ? L.pot[v] : 0;
-      done[i] = v >= k;
-      pred[i] = -1;
-      open[i] = v == s ? (uint64_t)DJ_BIAS << 12 : KEY_NONE;
-      fin[i] = KEY_NONE;
+      done |= (v >= k ? 1u : 0u) << i;
+      open[i] = v == s ? (uint64_t)DJ_BIAS << DJ_SHIFT : KEY_NONE;
+      if (v < k) {
+        L.dist[v] = DIST_NONE;
+        L.pred[v] = -1;
+        L.hop[v] = -1;
+        if (mode == 1 && v != s) pm = umin(pm, (uint64_t)(bound_term(v) + DJ_BIAS));
+      }
     }
+    int64_t pmin = 0;
+    if (mode == 1) {
+      pm = wave_min_u64(pm);
+      pmin = pm == KEY_NONE ? DJ_BIAS : (int64_t)pm - DJ_BIAS;   // k = 1: nothing to reach
+    }
+    int64_t best = INT64_MAX;                    // path mode: best s_in candidate so far
+    int64_t top = 0;                             // largest settled reduced label
+    int64_t D = -1;                              // reduced label the search stopped at
+    int nset = 0;
     for (int step = 0; step < k; ++step) {
       uint64_t m = open[0];
 #pragma unroll
       for (int i = 1; i < NPL; ++i) m = umin(m, open[i]);
       m = wave_min_u64(m);
-      if (m == KEY_NONE) break;                  // the rest is unreachable
+      if (m == KEY_NONE) break;                  // every reachable center is settled
+      const int64_t ml = (int64_t)(m >> DJ_SHIFT) - DJ_BIAS;
+      if (step > 0 && (mode == 0 ? ml >= 0 : ml + pmin > (best < -1 ? best : -1))) {
+        D = ml;
+        break;
+      }
       // the owner: first slot holding m, first lane of that slot
       int oi = -1;
       uint64_t om = 0;
@@ -717,46 +850,168 @@ __device__ __forceinline__ void dijkstra_wave(const InstView &I, const Lds &L, S
       }
       const int ol = __builtin_ctzll(om);
       const int u = ol + 64 * oi;
-      // the row of u and pot[u] in one round trip
+      // the row of u, this lane's potentials and pot[u] in one round trip
       uint32_t hw[NPL];
-      const uint32_t *row = Whi + 2 * (size_t)u * k;
+      const uint32_t *row = Whi + WS * (size_t)u * k;
 #pragma unroll
-      for (int i = 0; i < NPL; ++i) hw[i] = row[2 * (lane + 64 * i)];
+      for (int i = 0; i < NPL; ++i) hw[i] = row[WS * min(lane + 64 * i, k - 1)];
       const int64_t pot_u = L.pot[u];
-      const bool me = lane == ol;
-#pragma unroll
-      for (int i = 0; i < NPL; ++i) {
-        const bool hit = me && i == oi;
-        open[i] = hit ? KEY_NONE : open[i];
-        fin[i] = hit ? m : fin[i];
-        done[i] = done[i] || hit;
+      ++nset;
+      top = ml > top ? ml : top;
+      if (lane == ol) {
+        L.dist[u] = ml - pot_s + pot_u;
+        L.pred[u] = u == s ? -1 : (int32_t)(m & 511);
+        L.hop[u] = (int32_t)((m >> 9) & 511);
       }
-      const uint64_t base = m + 1;               // one more edge
+      if (mode == 1 && u != s) {
+        const int64_t c = ml + bound_term(u);    // s_in's candidate through u
+        best = c < best ? c : best;
+      }
+      done |= (lane == ol ? 1u : 0u) << oi;
+      // one more edge, from u
+      const uint64_t base = (m & ~(uint64_t)511) + (1u << 9) + (uint32_t)u;
 #pragma unroll
       for (int i = 0; i < NPL; ++i) {            // branch-free: selects only
-        const bool valid = !done[i] && hw[i] != 0xffffffffu;
-        const int64_t w = (int64_t)(int32_t)(hw[i] ^ 0x80000000u) + (pot_u - pv[i]);
-        const uint64_t c = valid ? base + ((uint64_t)w << 12) : KEY_NONE;
-        const bool lt = c < open[i];
-        const bool tie = valid && c == open[i] && u < pred[i];
-        open[i] = lt ? c : open[i];
-        pred[i] = (lt || tie) ? u : pred[i];
+        const bool valid = !((done >> i) & 1u) && hw[i] != 0xffffffffu;
+        const int64_t w = (int64_t)(int32_t)(hw[i] ^ 0x80000000u) + (pot_u - L.pot[min(lane + 64 * i, k - 1)]);
+        const uint64_t c = valid ? base + ((uint64_t)w << DJ_SHIFT) : KEY_NONE;
+        open[i] = ((done >> i) & 1u) ? KEY_NONE : umin(open[i], c);
       }
     }
-    const int64_t pot_s = L.pot[s];
-    uint32_t deepest = 0;
+    if (D < 0) D = top;                          // everything reachable was settled
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
       const int v = lane + 64 * i;
       if (v >= k) continue;
-      const bool r = fin[i] != KEY_NONE;
-      L.dist[v] = r ? (int64_t)(fin[i] >> 12) - DJ_BIAS - pot_s + pv[i] : DIST_NONE;
-      L.pred[v] = r ? pred[i] : -1;
-      L.hop[v] = r ? (int32_t)(fin[i] & 4095) : -1;
-      deepest = r ? max(deepest, (uint32_t)(fin[i] & 4095)) : deepest;
+      const bool settled = (done >> i) & 1u;
+      const int64_t p2 = settled ? L.dist[v] : L.pot[v] - pot_s + D;
+      L.pot2[v] = p2 < POT_FLOOR ? POT_FLOOR : p2;
     }
-    deepest = ~wave_min_u32(~deepest);   // wave maximum
-    if (lane == 0) S.maxhop = (int32_t)deepest;
+    if (lane == 0) {
+      S.settled[mode] += (nset * 16 - S.settled[mode]) / 8;
+      S.stats[ST_DJ_SETTLED] += nset;
+      const int64_t spent = now() - t_start;
+      S.stats[ST_T_DIJKSTRA] += spent;
+      const int64_t per = spent * 16 / (nset > 0 ? nset : 1);
+      S.step_t += ((int32_t)min(per, (int64_t)INT32_MAX / 2) - S.step_t) / 8;
+      S.nsearch += 1;
+    }
+  }
+  __syncthreads();
+}
+
+// The same bounded search in Dijkstra order for k > 128, over the
+// workgroup's wavefronts: wave w owns centers 64 w .. 64 w + 63, one per
+// lane.  A step takes each wave's smallest open key (and its
+// center, the first lane holding it) into LDS, one barrier, then every thread
+// picks the smallest over the waves (the first wave on equal keys, so the
+// center settled is the same as by one wavefront scanning its slots in
+// order), reads its own column of the settled center's row and relaxes it.
+// The per-wave minima are double-buffered by step parity: a wave writes the
+// next step's entry only after the barrier that every wave passes after
+// reading this step's.  (k <= 512: the key holds edges and predecessor in
+// 9 bits each.)
+constexpr int DJ_MAX_K = 512;
+template <bool WLDS>
+__device__ __forceinline__ void dijkstra_waves(const InstView &I, const Lds &L, Scalars &S, int s,
+                                               int mode) {
+  const int k = I.k;
+  const int tid = threadIdx.x;
+  int lane = tid & 63;
+  asm volatile("" : "+v"(lane));               // see dijkstra_bounded
+  const int wave = tid >> 6;
+  const int nw = (k + 63) >> 6;                  // waves that own centers
+  const int v = wave * 64 + lane;
+  const bool mine = v < k;
+  constexpr int WS = WLDS ? 2 : 1;
+  const uint32_t *Whi = WLDS ? reinterpret_cast<const uint32_t *>(L.W) + 1 : L.wh;
+  uint64_t *wkey = L.wmin;                       // [2][NT / 64] per-wave minima
+  int32_t *wnode = L.mrow;                       // [2][NT / 64] their centers (k + 1 >= 32)
+  const int64_t t_start = tid == 0 ? now() : 0;
+  const int64_t pot_s = L.pot[s];
+  const int64_t q_anchor =
+      mode == 0 ? 0 : penalty_at(I, L, s, L.load[s] > L.cap[s] ? (int64_t)L.load[s] - L.cap[s] : 1);
+  auto bound_term = [&](int u) -> int64_t {
+    const int64_t w =
+        (L.load[u] >= L.cap[u] ? penalty_at(I, L, u, (int64_t)L.load[u] - L.cap[u] + 1) : 0) - q_anchor;
+    return L.pot[u] + w - pot_s;
+  };
+  const int64_t pv = mine ? L.pot[v] : 0;
+  uint64_t open = (mine && v == s) ? (uint64_t)DJ_BIAS << DJ_SHIFT : KEY_NONE;
+  bool done = !mine;                             // settled, or no center here
+  if (mine) {
+    L.dist[v] = DIST_NONE;
+    L.pred[v] = -1;
+    L.hop[v] = -1;
+  }
+  int64_t pmin = 0;
+  if (mode == 1) {
+    const uint64_t pm = wave_min_u64((mine && v != s) ? (uint64_t)(bound_term(v) + DJ_BIAS) : KEY_NONE);
+    if (lane == 0) wkey[NT / 64 + wave] = pm;
+    __syncthreads();
+    uint64_t g = KEY_NONE;
+    for (int j = 0; j < nw; ++j) g = umin(g, wkey[NT / 64 + j]);
+    pmin = g == KEY_NONE ? DJ_BIAS : (int64_t)g - DJ_BIAS;   // k = 1: nothing to reach
+  }
+  int64_t best = INT64_MAX;
+  int64_t top = 0;
+  int64_t D = -1;
+  int nset = 0;
+  for (int step = 0; step < k; ++step) {
+    const int b = (step & 1) * (NT / 64);
+    const uint64_t lm = wave_min_u64(open);
+    const uint64_t hold = __ballot(open == lm);
+    if (lane == 0) {
+      wkey[b + wave] = lm;
+      wnode[b + wave] = wave * 64 + (hold ? __builtin_ctzll(hold) : 0);
+    }
+    __syncthreads();
+    uint64_t m = KEY_NONE;
+    int u = 0;
+    for (int j = 0; j < nw; ++j) {
+      const uint64_t x = wkey[b + j];
+      if (x < m) { m = x; u = wnode[b + j]; }
+    }
+    if (m == KEY_NONE) break;                    // every reachable center is settled
+    const int64_t ml = (int64_t)(m >> DJ_SHIFT) - DJ_BIAS;
+    if (step > 0 && (mode == 0 ? ml >= 0 : ml + pmin > (best < -1 ? best : -1))) {
+      D = ml;
+      break;
+    }
+    const uint32_t hw = mine ? Whi[WS * ((int64_t)u * k + v)] : 0xffffffffu;
+    const int64_t pot_u = L.pot[u];
+    ++nset;
+    top = ml > top ? ml : top;
+    if (v == u) {
+      L.dist[u] = ml - pot_s + pot_u;
+      L.pred[u] = u == s ? -1 : (int32_t)(m & 511);
+      L.hop[u] = (int32_t)((m >> 9) & 511);
+      done = true;
+      open = KEY_NONE;
+    }
+    if (mode == 1 && u != s) {
+      const int64_t c = ml + bound_term(u);      // s_in's candidate through u
+      best = c < best ? c : best;
+    }
+    if (!done && hw != 0xffffffffu) {
+      const uint64_t base = (m & ~(uint64_t)511) + (1u << 9) + (uint32_t)u;
+      const int64_t w = (int64_t)(int32_t)(hw ^ 0x80000000u) + (pot_u - pv);
+      open = umin(open, base + ((uint64_t)w << DJ_SHIFT));
+    }
+  }
+  if (D < 0) D = top;                            // everything reachable was settled
+  if (mine) {
+    const int64_t p2 = done ? L.dist[v] : pv - pot_s + D;
+    L.pot2[v] = p2 < POT_FLOOR ? POT_FLOOR : p2;
+  }
+  if (tid == 0) {
+    S.settled[mode] += (nset * 16 - S.settled[mode]) / 8;
+    S.stats[ST_DJ_SETTLED] += nset;
+    const int64_t spent = now() - t_start;
+    S.stats[ST_T_DIJKSTRA] += spent;
+    const int64_t per = spent * 16 / (nset > 0 ? nset : 1);
+    S.step_t += ((int32_t)min(per, (int64_t)INT32_MAX / 2) - S.step_t) / 8;
+    S.nsearch += 1;
   }
   __syncthreads();
 }
@@ -766,19 +1021,35 @@ __device__ __forceinline__ void dijkstra_wave(const InstView &I, const Lds &L, S
 // of the cycle search just run on the same W.  Returns true when nothing was
 // applied and the search succeeded: the labels in LDS then describe the
 // current W.
-// Without labels the search runs in Dijkstra order when the node potentials
-// allow it (cycle mode: feasible except on edges leaving s, which is all an
-// insert into s can break; path mode: feasible), else as Bellman-Ford rounds.
+// Without labels the search runs in Dijkstra order, bounded to the centers
+// that can matter for s_in, when the node potentials allow it (cycle mode:
+// feasible except on edges leaving s, which is all an insert into s can
+// break; path mode: feasible) and the cost model prefers it, else as
+// Bellman-Ford rounds.
 template <bool WLDS>
 __device__ __forceinline__ bool refine(const InstView &I, const Lds &L, Scalars &S, int s, int mode,
                                        bool have_labels) {
   const int k = I.k;
   const int tid = threadIdx.x;
-  // cost model: a search takes (deepest hop + 1) Bellman-Ford rounds or k
-  // Dijkstra steps, and a round costs `ratio` steps (both x16; the default
-  // is 4 steps, the autotuner measures it)
-  const bool dijkstra = !have_labels && WLDS && S.pot_ok && k <= 64 * DJ_MAX_NPL &&
-                        (int64_t)S.depth * S.ratio > 256 * (int64_t)k;
+  // cost model: a Bellman-Ford search takes `depth` rounds and one in
+  // Dijkstra order `settled` steps (running means per mode, x16), and a round
+  // costs `ratio` steps (x16): a fixed value, or by default the ratio of the
+  // measured times of a round and a step.  The automatic choice first
+  // measures each kind in each mode, and then takes the other kind in one
+  // search of every 64, so that both measurements follow the workload.
+  bool prefer;
+  if (S.ratio != SEARCH_RATIO_AUTO) {
+    prefer = (int64_t)S.depth[mode] * S.ratio > 16 * (int64_t)S.settled[mode];
+  } else if (S.depth[mode] == 0 || S.round_t == 0) {
+    prefer = false;                           // Bellman-Ford not yet measured in this mode
+  } else if (S.settled[mode] == 0 || S.step_t == 0) {
+    prefer = true;                            // nor Dijkstra order
+  } else {
+    const int64_t ratio = 16 * (int64_t)S.round_t / S.step_t;
+    prefer = (int64_t)S.depth[mode] * ratio > 16 * (int64_t)S.settled[mode];
+    if ((S.nsearch & 63) == 63) prefer = !prefer;
+  }
+  const bool dijkstra = !have_labels && S.pot_ok && k <= DJ_MAX_K && prefer;
   if (tid == 0) {
     S.stats[mode == 0 ? ST_CYC_SEARCH : ST_PATH_SEARCH] += 1;
     if (have_labels) S.stats[ST_PATH_DERIVED] += 1;
@@ -787,20 +1058,19 @@ __device__ __forceinline__ bool refine(const InstView &I, const Lds &L, Scalars 
   if (have_labels) {
     sin_from_labels(I, L, s, 1);
   } else if (dijkstra) {
-    if (k <= 64) dijkstra_wave<1>(I, L, S, s);
-    else if (k <= 128) dijkstra_wave<2>(I, L, S, s);
-    else dijkstra_wave<DJ_MAX_NPL>(I, L, S, s);
+    if (k <= 64) dijkstra_bounded<WLDS, 1>(I, L, S, s, mode);
+    else if (k <= 128) dijkstra_bounded<WLDS, 2>(I, L, S, s, mode);
+    else dijkstra_waves<WLDS>(I, L, S, s, mode);
     if (S.status != 0) return false;
-    if (tid == 0) S.depth += ((S.maxhop + 1) * 16 - S.depth) / 8;
     sin_from_labels(I, L, s, mode);
   } else {
-    if (!bellman_ford<WLDS>(I, L, S, s)) return false;
+    if (!bellman_ford<WLDS>(I, L, S, s, mode)) return false;
     sin_from_labels(I, L, s, mode);
   }
   const int64_t D = L.dist[k];
   if (D == DIST_NONE || D >= 0) {             // only strictly negative refinements apply
-    if (!have_labels) adopt_potential(I, L, S, s);
-    return true;
+    if (!have_labels) take_potential<WLDS>(I, L, S, s, 0);
+    return !dijkstra;                         // complete labels: Bellman-Ford rounds only
   }
   if (tid == 0) {
     S.pot_ok = 0;                             // W is about to change
@@ -869,7 +1139,7 @@ __device__ __forceinline__ bool refine(const InstView &I, const Lds &L, Scalars 
   }
   if (tid == 0) S.stats[ST_T_RESCAN] += now() - t0;
   __syncthreads();
-  if (S.status == 0) retry_potential(I, L, S, s, nmov);
+  if (S.status == 0) take_potential<WLDS>(I, L, S, s, nmov);
   return false;
 }
 
@@ -914,6 +1184,7 @@ __device__ __forceinline__ Lds carve_lds(const InstView &I, unsigned char *lds) 
   L.front1 = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
   p = lds + (((p - lds) + 7) & ~(ptrdiff_t)7);   // offsets keep the LDS address space
   L.pot = reinterpret_cast<int64_t *>(p); p += (size_t)k * 8;
+  L.pot2 = reinterpret_cast<int64_t *>(p); p += (size_t)k * 8;
   L.load = reinterpret_cast<int32_t *>(p); p += (size_t)k * 4;
   L.cap = reinterpret_cast<int32_t *>(p); p += (size_t)k * 4;
   L.pen = reinterpret_cast<int32_t *>(p); p += (size_t)k * 4;
@@ -944,9 +1215,12 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
     // the potential is not kept between launches: the first search rebuilds it
     // (an empty table is certified by the zero potential)
     S.pot_ok = r_begin == 0;
-    S.depth = 0;
+    S.depth[0] = S.depth[1] = 0;
+    S.settled[0] = S.settled[1] = 0;
+    S.round_t = S.step_t = 0;
+    S.nsearch = 0;
     S.jflags[0] = S.jflags[1] = 0;
-    S.ratio = (int32_t)min(max(I.scalars[SC_RATIO], (int64_t)0), MAX_SEARCH_RATIO);
+    S.ratio = (int32_t)min(max(I.scalars[SC_RATIO], SEARCH_RATIO_AUTO), MAX_SEARCH_RATIO);
     S.obj = I.scalars[SC_OBJECTIVE];
     S.status = (int32_t)I.scalars[SC_STATUS];
     for (int j = 0; j < SC_NSTATS; ++j) S.stats[j] = I.scalars[SC_STAT0 + j];

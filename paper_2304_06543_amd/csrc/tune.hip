@@ -2,13 +2,17 @@
 // not change any result and records the fastest for this process.
 //
 // * Search choice (lbdd_tune_search).  A refinement search that may run in
-//   Dijkstra order runs so when (deepest hop + 1) x ratio > k, i.e. when the
-//   Bellman-Ford rounds it would need cost more than k Dijkstra steps.  The
-//   ratio is the cost of one round in steps; it depends on k and the workload.
+//   Dijkstra order runs so when the Bellman-Ford rounds it would need (a
+//   running mean) cost more than the Dijkstra steps it would need (another
+//   running mean), a round costing `ratio` steps.  By default the solve
+//   measures the ratio itself from the device times of both kinds; the
+//   candidates are that automatic ratio, always Bellman-Ford (0), a fixed
+//   ratio (4 steps) and Dijkstra whenever the potentials allow it (2^20).
 //   The tuner solves (a prefix of) the caller's instance once per candidate
-//   ratio and keeps the fastest, if it beats the default by more than 2 %; instances created afterwards with the same k
-//   start with it (lbdd_set_option overrides it per instance), and so do the
-//   instances of a batched launch, which read it from their own state.
+//   and keeps the fastest, if it beats the default by more than 2 %;
+//   instances created afterwards with the same k start with it
+//   (lbdd_set_option overrides it per instance), and so do the instances of
+//   a batched launch, which read it from their own state.
 // * Scan tiles (lbdd_tune_best_transfers).  The whole-matrix scan can give a
 //   row 1 to 64 lanes, each lane 1 to 32 column groups, and run one or two
 //   resident waves of workgroups.  The tuner times every shape that fits k on
@@ -72,7 +76,7 @@ int lbdd_tune_search(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap
   if (!ratio_out) return fail(LBDD_E_INVAL, "ratio_out is NULL");
   if (iters < 1) return fail(LBDD_E_INVAL, "iters < 1");
   if (count < 0 || (count > 0 && !ms_out)) return fail(LBDD_E_INVAL, "ms_out/count");
-  static const int64_t CAND[] = {0, 32, 64, 128, lbdd::MAX_SEARCH_RATIO};
+  static const int64_t CAND[] = {lbdd::SEARCH_RATIO_AUTO, 0, 64, lbdd::MAX_SEARCH_RATIO};
   constexpr int NC = sizeof(CAND) / sizeof(CAND[0]);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   Timer tm;

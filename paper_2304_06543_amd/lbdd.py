@@ -26,7 +26,13 @@ STATS = ("cycles", "paths", "moves", "cycle_searches", "path_searches", "bf_roun
          "rows_scanned", "iterations", "cycle_searches_skipped",
          "ticks_allot", "ticks_cycle", "ticks_path", "ticks_rescan", "refills",
          "tick_first", "tick_last", "relaxations", "paths_derived", "dijkstra",
-         "potentials_kept", "timer_khz")
+         "potentials_kept", "dijkstra_settled", "potential_repairs", "repair_rounds",
+         "ticks_dijkstra", "ticks_bf", "ticks_potentials", "timer_khz")
+
+# search ratios lbdd_tune_search times, in order: measured during the solve,
+# always Bellman-Ford, a fixed 4 steps per round, Dijkstra whenever allowed
+SEARCH_AUTO = -1
+SEARCH_CANDIDATES = (SEARCH_AUTO, 0, 64, 1 << 20)
 
 # every symbol include/lbdd.h declares
 EXPORTS = ("lbdd_create", "lbdd_solve", "lbdd_solve_iters", "lbdd_solve_batch", "lbdd_objective",
@@ -378,7 +384,8 @@ def best_transfers_batch(cms, assigns, ranks, Ws=None, work=None, stream=None, r
 
 def tune_search(cm, capacity, penalty, iters: int, stream=None):
     """Autotune the search choice for this k on a prefix of `iters`
-    iterations (lbdd_tune_search).  Returns (ratio, [ms per candidate])."""
+    iterations (lbdd_tune_search).  Returns (ratio, [ms per candidate]), the
+    candidates being SEARCH_CANDIDATES."""
     k, n, ptr, flags, cap, pen, keep = _create_args(cm, capacity, penalty)
     ratio = C.c_int64()
     ms = (C.c_float * 8)()

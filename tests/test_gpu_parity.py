@@ -146,10 +146,11 @@ def test_config_c2_bit_exact_against_stored_oracle(lb):
 
 def test_every_search_kind_runs_bit_exact(lb):
     """The solver answers a refinement search in one of several exact ways:
-    Bellman-Ford rounds, Dijkstra order on feasible node potentials, the
-    labels of a cycle search that applied nothing, or no search at all when
-    the potentials certify there is no negative cycle.  These instances use
-    every one of them, and the results still equal the oracle's."""
+    Bellman-Ford rounds, bounded Dijkstra order on feasible node potentials
+    (repaired after refinements where needed), the labels of a cycle search
+    that applied nothing, or no search at all when the potentials certify
+    there is no negative cycle.  These instances use every one of them, and
+    the results still equal the oracle's."""
     seen = {}
     for seed, k in ((41, 12), (42, 40), (43, 100)):
         inst = L.random_small(k=k, n=4000, seed=seed, cm_hi=300, pen_hi=400)
@@ -158,7 +159,7 @@ def test_every_search_kind_runs_bit_exact(lb):
         obj, a, st = gpu_solve(lb, inst)
         assert obj == ref.objective and np.array_equal(a, ref.assign)
         for key in ("bf_rounds", "dijkstra", "paths_derived", "potentials_kept",
-                    "cycle_searches_skipped", "cycles", "paths"):
+                    "potential_repairs", "cycle_searches_skipped", "cycles", "paths"):
             seen[key] = seen.get(key, 0) + st[key]
     say("search kinds", seen)
     assert all(v > 0 for v in seen.values()), seen
@@ -280,15 +281,17 @@ def test_c3_prefix_bit_exact_and_invariants(lb):
 
 
 # ---------------------------------------------------- options and autotuner
-@pytest.mark.parametrize("k", [12, 40, 100, 131])
+@pytest.mark.parametrize("k", [12, 40, 100, 131, 200, 300, 500])
 def test_search_ratio_extremes_bit_exact(lb, k):
-    """All Bellman-Ford rounds (ratio 0) and Dijkstra order whenever the
-    potentials allow it (ratio 2^20) reach the oracle's allotment."""
+    """All Bellman-Ford rounds (ratio 0), Dijkstra order whenever the
+    potentials allow it (ratio 2^20, bounded searches; with the table in
+    global memory for k > 136) and the measured choice (-1) reach the
+    oracle's allotment."""
     import torch
     inst = L.random_small(k=k, n=3000, seed=900 + k, cm_hi=400, pen_hi=300)
     say("search ratio", inst.name)
     ref = oracle.solve(*inst.arrays())
-    for ratio in (0, 1 << 20):
+    for ratio in (0, 1 << 20, lb.SEARCH_AUTO):
         with lb.Instance(torch.from_numpy(inst.cm).cuda(), inst.cap, inst.pen) as I:
             I.set_option(lb.OPT_SEARCH_RATIO, ratio)
             assert I.get_option(lb.OPT_SEARCH_RATIO) == ratio
@@ -298,15 +301,15 @@ def test_search_ratio_extremes_bit_exact(lb, k):
         assert obj == ref.objective and np.array_equal(a, ref.assign)
         if ratio == 0:
             assert st["dijkstra"] == 0
-        elif k <= 130:   # W in LDS: Dijkstra order is available
-            assert st["dijkstra"] > 0
+        elif ratio == 1 << 20:
+            assert st["dijkstra"] > 0 and st["dijkstra_settled"] >= st["dijkstra"]
 
 
 def test_set_option_rejects_bad_values(lb):
     import torch
     inst = L.random_small(k=5, n=50, seed=3)
     with lb.Instance(torch.from_numpy(inst.cm).cuda(), inst.cap, inst.pen) as I:
-        for opt, val in ((lb.OPT_SEARCH_RATIO, -1), (lb.OPT_SEARCH_RATIO, (1 << 20) + 1), (99, 1)):
+        for opt, val in ((lb.OPT_SEARCH_RATIO, -2), (lb.OPT_SEARCH_RATIO, (1 << 20) + 1), (99, 1)):
             with pytest.raises(lb.LbddError) as e:
                 I.set_option(opt, val)
             assert e.value.code == lb.E_INVAL
@@ -320,8 +323,8 @@ def test_tune_search_records_ratio_and_stays_exact(lb):
     say("tune search", inst.name)
     ratio, ms = lb.tune_search(torch.from_numpy(inst.cm).cuda(), inst.cap, inst.pen, iters=3000)
     say("  ratio", ratio, "ms", ms)
-    assert len(ms) == 5 and all(t > 0 for t in ms)
-    assert ratio in (0, 32, 64, 128, 1 << 20)
+    assert len(ms) == len(lb.SEARCH_CANDIDATES) and all(t > 0 for t in ms)
+    assert ratio in lb.SEARCH_CANDIDATES
     ref = oracle.solve(*inst.arrays())
     with lb.Instance(torch.from_numpy(inst.cm).cuda(), inst.cap, inst.pen) as I:
         assert I.get_option(lb.OPT_SEARCH_RATIO) == ratio

@@ -76,3 +76,64 @@ def test_labels_need_only_the_checked_edges(seed):
     full = feasible(W2, p)
     short = feasible(W2, p, rows=moved) and feasible(W2, p, col=s)
     assert full == short, seed
+
+
+def _repair(W, p, tails):
+    """The kernel's repair: labels start at 0 everywhere, the first round
+    relaxes out of the tails of failed edges, later rounds out of the centers
+    whose label dropped; returns p + lab shifted to p[s] + lab[s] = 0, or None
+    without convergence."""
+    k = W.shape[0]
+    lab = [0] * k
+    front = sorted(set(tails))
+    for _ in range(k + 1):
+        nxt = set()
+        for u in front:
+            for v in range(k):
+                if u == v or W[u, v] == pins.KEY_NONE:
+                    continue
+                c = lab[u] + pins.key_delta(W[u, v]) + p[u] - p[v]
+                if c < lab[v]:
+                    lab[v] = c
+                    nxt.add(v)
+        if not nxt:
+            return [p[v] + lab[v] for v in range(k)]
+        front = sorted(nxt)
+    return None
+
+
+@pytest.mark.parametrize("seed", range(120))
+def test_repair_from_failed_tails_restores_feasibility(seed):
+    """After an applied refinement changes some rows, potentials that fail the
+    check on those rows are repaired from the failed edges' tails alone; the
+    result is feasible on every edge whenever the table has no negative cycle
+    (Lemmas 1 and 2), and the repair then always converges."""
+    rng = np.random.default_rng(1000 + seed)
+    k = int(rng.integers(2, 10))
+    s = int(rng.integers(0, k))
+    W = _table(rng, k, s)
+    z = np.zeros(k, np.int32)
+    dist, _, _ = oracle.refine_search(W, s, 0, z, z, np.ones(k, np.int32))
+    if any(dist[v] == oracle.DIST_NONE for v in range(k)) or not feasible(W, [int(x) for x in dist[:k]]):
+        return                                   # a negative cycle through s: not this case
+    p = [int(x) for x in dist[:k]]
+    moved = {int(c) for c in rng.choice(k, size=int(rng.integers(1, k + 1)), replace=False)}
+    W2 = W.copy()
+    for u in moved:
+        for v in range(k):
+            if u != v and rng.random() < 0.6:
+                W2[u, v] = _key(pins.key_delta(W[u, v]) - int(rng.integers(0, 6))
+                                if W[u, v] != pins.KEY_NONE else int(rng.integers(-4, 9)))
+    if pins.has_negative_cycle(W2):
+        return
+    rows = moved | {s}
+    tails = [u for u in range(k) for v in range(k)
+             if u != v and W2[u, v] != pins.KEY_NONE and (u in rows or v == s)
+             and p[v] > p[u] + pins.key_delta(W2[u, v])]
+    # the checked rows and column s hold every failed edge
+    all_failed = [u for u in range(k) for v in range(k)
+                  if u != v and W2[u, v] != pins.KEY_NONE and p[v] > p[u] + pins.key_delta(W2[u, v])]
+    assert set(all_failed) <= set(tails)
+    q = _repair(W2, p, tails)
+    assert q is not None, seed
+    assert feasible(W2, q), seed
