@@ -966,11 +966,24 @@ __device__ __forceinline__ void dijkstra_waves(const InstView &I, const Lds &L, 
       wnode[b + wave] = wave * 64 + (hold ? __builtin_ctzll(hold) : 0);
     }
     __syncthreads();
+    // every wave wrote its entry (all ones without an open center): read the
+    // entries of the DJ_MAX_K / 64 waves that can own centers at once, then
+    // take the first smallest
+    constexpr int MW = DJ_MAX_K / 64;
+    uint64_t xk[MW];
+    int32_t xn[MW];
+#pragma unroll
+    for (int j = 0; j < MW; ++j) {
+      xk[j] = wkey[b + j];
+      xn[j] = wnode[b + j];
+    }
     uint64_t m = KEY_NONE;
     int u = 0;
-    for (int j = 0; j < nw; ++j) {
-      const uint64_t x = wkey[b + j];
-      if (x < m) { m = x; u = wnode[b + j]; }
+#pragma unroll
+    for (int j = MW - 1; j >= 0; --j) {
+      const bool le = xk[j] <= m;
+      m = le ? xk[j] : m;
+      u = le ? xn[j] : u;
     }
     if (m == KEY_NONE) break;                    // every reachable center is settled
     const int64_t ml = (int64_t)(m >> DJ_SHIFT) - DJ_BIAS;
