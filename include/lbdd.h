@@ -333,6 +333,25 @@ int lbdd_best_transfers(int32_t k, int64_t n, const int32_t *cm, const int32_t *
                         const int32_t *rank, uint64_t *W, void *work, uint32_t flags,
                         void *hip_stream);
 
+/* lbdd_best_transfers without a workspace argument and without allocating,
+ * for callers that cannot allocate device memory: code being captured into
+ * a HIP graph, tight serving loops, harnesses that forbid allocation.  The
+ * arguments and the result are those of lbdd_best_transfers; the workspace
+ * is a fixed array of LBDD_NOALLOC_SCRATCH_BYTES (16 MiB) inside the library,
+ * one per GPU, held from the library's first use on that GPU until the
+ * process ends.  The call makes no hipMalloc/hipFree and no allocating
+ * library call; its kernels clear what must start at zero.
+ *   flags  LBDD_SCAN_REUSE_GROUPING: the scratch still holds the grouping of
+ *          this same (assign, rank) from the last call on this GPU
+ * Every call on one GPU shares that GPU's scratch and leaves its grouping
+ * there: calls that overlap on one GPU (several streams, threads) race.
+ * Asynchronous on `hip_stream`.  Errors: LBDD_E_INVAL (as lbdd_best_transfers,
+ * and when lbdd_best_transfers_work_bytes(k, n) exceeds the scratch: about
+ * n > 2,000,000 units), LBDD_E_DEVICE. */
+#define LBDD_NOALLOC_SCRATCH_BYTES (16 << 20)
+int lbdd_best_transfers_noalloc(int32_t k, int64_t n, const int32_t *cm, const int32_t *assign,
+                                const int32_t *rank, uint64_t *W, uint32_t flags, void *hip_stream);
+
 /* The tables of many allotments at once (the batched form of the scan above;
  * LBDD_SCAN_REUSE_GROUPING is defined there):
  * item i has k[i] centers (1 <= k[i] <= LBDD_MAX_K) and n[i] >= 0 units, and

@@ -43,7 +43,8 @@ EXPORTS = ("lbdd_create", "lbdd_solve", "lbdd_solve_iters", "lbdd_solve_batch", 
            "lbdd_server_destroy", "lbdd_set_option", "lbdd_get_option", "lbdd_tune_search",
            "lbdd_tune_best_transfers", "lbdd_create_strict", "lbdd_centers",
            "lbdd_create_penalty_table", "lbdd_road_cm_work_bytes", "lbdd_road_cost_matrix",
-           "lbdd_best_transfers_batch_work_bytes", "lbdd_best_transfers_batch")
+           "lbdd_best_transfers_batch_work_bytes", "lbdd_best_transfers_batch",
+           "lbdd_best_transfers_noalloc")
 JOB_QUEUED, JOB_RUNNING, JOB_DONE = 0, 1, 2
 SERVER_STATS = ("submitted", "admitted", "finished", "failed", "kernel_launches",
                 "peak_jobs", "peak_bytes", "bytes_now", "workers")
@@ -98,6 +99,7 @@ def load(path: str = LIB_PATH):
         "lbdd_road_cost_matrix": ([I32, P, P, P, I32, P, I64, P, P, P, P], C.c_int),
         "lbdd_best_transfers_batch_work_bytes": ([I32, P, P], C.c_size_t),
         "lbdd_best_transfers_batch": ([I32, P, P, P, P, P, P, P, U32, P], C.c_int),
+        "lbdd_best_transfers_noalloc": ([I32, I64, P, P, P, P, U32, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -339,6 +341,29 @@ def best_transfers(cm, assign, rank, W=None, work=None, stream=None, reuse_group
                                       C.c_void_p(W.data_ptr()), C.c_void_p(work.data_ptr()),
                                       SCAN_REUSE_GROUPING if reuse_grouping else 0,
                                       _stream_ptr(stream)))
+    return W
+
+
+NOALLOC_SCRATCH_BYTES = 16 << 20
+
+
+def best_transfers_noalloc(cm, assign, rank, W, stream=None, reuse_grouping=False):
+    """best_transfers through lbdd_best_transfers_noalloc: the workspace is
+    the library's fixed per-GPU scratch and nothing is allocated (W, [k][k]
+    int64 on the device, is the caller's).  reuse_grouping: the scratch holds
+    the grouping of the same assign/rank from the last call on this GPU."""
+    import torch
+    n, k = cm.shape
+    for t in (cm, assign, rank):
+        if not (t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()):
+            raise ValueError("cm, assign and rank must be contiguous int32 cuda tensors")
+    if not (W.is_cuda and W.dtype == torch.int64 and W.is_contiguous() and W.numel() == k * k):
+        raise ValueError("W must be a contiguous int64 cuda tensor of k*k entries")
+    _check(load().lbdd_best_transfers_noalloc(int(k), int(n), C.c_void_p(cm.data_ptr()),
+                                              C.c_void_p(assign.data_ptr()), C.c_void_p(rank.data_ptr()),
+                                              C.c_void_p(W.data_ptr()),
+                                              SCAN_REUSE_GROUPING if reuse_grouping else 0,
+                                              _stream_ptr(stream)))
     return W
 
 
