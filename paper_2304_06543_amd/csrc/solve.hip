@@ -96,6 +96,7 @@ struct Scalars {
   int32_t round_t;  // running mean of the device ticks per Bellman-Ford round, x16
   int32_t step_t;   // running mean of the device ticks per Dijkstra step, x16
   int32_t nsearch;  // searches run (Bellman-Ford or Dijkstra order)
+  uint64_t bound;   // pruned Bellman-Ford: biased bound term (see bellman_ford)
   int32_t jflags[2];  // join_center's result, by iteration parity
 };
 
@@ -501,6 +502,15 @@ __device__ __forceinline__ uint64_t strict_entry(const InstView &I, const Lds &L
   return L.load[u] < L.cap[u] ? umin(head, DUMMY_KEY) : head;
 }
 
+// Penalty of the j-th unit (j >= 1) beyond the capacity of center s: the
+// constant pen[s], or the j-th value of the center's table (its last value
+// for every later unit).
+__device__ inline int64_t penalty_at(const InstView &I, const Lds &L, int s, int64_t j) {
+  if (!I.pval) return L.pen[s];
+  const int64_t b = I.poff[s], len = I.poff[s + 1] - b;
+  return I.pval[b + (j < len ? j : len) - 1];
+}
+
 // Label of a center during a search, packed so that one unsigned min orders
 // by (distance, edges, predecessor): ((dist + 2^41) << 22) | (edges << 11) |
 // pred.  Simple paths have at most k - 1 <= 2047 edges of |delta| < 2^30, so
@@ -529,8 +539,22 @@ __device__ inline uint64_t lab_pack(int64_t dist, int32_t edges, int32_t pred) {
 // stamp (taken by atomic exchange) shows that another thread already has.
 // Only the key's high word of W (delta + 2^31, all ones = no edge) is read.
 // Returns false (and sets the status) on a change in round k+1.
+//
+// Pruned (prune: the node potentials pot are feasible, on every edge except
+// those out of s in cycle mode): a center whose label's reduced value
+// r(v) = dist(v) + pot[s] - pot[v] is not below a bound Db cannot lead to a
+// negative s_in label, so it enters no frontier (its label may still drop).
+// Cycle mode: Db = 0 (an edge into s is feasible, so a cycle through v costs
+// at least r(v)).  Path mode: Db = -Pmin, Pmin the smallest pot[u] +
+// w(u, s_in) - pot[s] (s_in's candidate through u is at least r(u) + Pmin).
+// Reduced weights beyond the first hop are non-negative, so every center
+// that matters (r < Db) has all of a shortest path's centers below Db too,
+// and gets its exact label and predecessor; the others get DIST_NONE.  The
+// candidate potentials pot2 follow the rule of the bounded Dijkstra search
+// with D = max(Db, 0).
 template <bool WLDS>
-__device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Scalars &S, int s, int mode) {
+__device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Scalars &S, int s, int mode,
+                                             bool prune) {
   const int k = I.k;
   const int tid = threadIdx.x;
   const int64_t t_start = tid == 0 ? now() : 0;
@@ -540,6 +564,7 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
   const uint32_t *Whi = WLDS ? reinterpret_cast<const uint32_t *>(L.W) + 1 : L.wh;
   uint64_t *lab = L.red;                      // packed labels
   int32_t *stamp = L.hop;                     // last round whose frontier took the center
+  const int64_t pot_s = prune ? L.pot[s] : 0;
   for (int v = tid; v <= k; v += NT) {
     lab[v] = (v == s) ? lab_pack(0, 0, 0) : KEY_NONE;
     stamp[v] = 0;
@@ -549,8 +574,25 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
     S.nfront[1] = 1;
     S.nfront[2] = 0;
     L.front1[0] = s;
+    S.bound = prune && mode == 1 ? KEY_NONE : (uint64_t)DIST_BIAS;   // Db = 0 in cycle mode
   }
   __syncthreads();
+  if (prune && mode == 1) {
+    const int64_t q_anchor = penalty_at(I, L, s, L.load[s] > L.cap[s] ? (int64_t)L.load[s] - L.cap[s] : 1);
+    for (int u = tid; u < k; u += NT) {
+      if (u == s) continue;
+      const int64_t w =
+          (L.load[u] >= L.cap[u] ? penalty_at(I, L, u, (int64_t)L.load[u] - L.cap[u] + 1) : 0) - q_anchor;
+      // -(pot[u] + w - pot[s]), biased: the largest term gives Db = -Pmin
+      const uint64_t b = (uint64_t)(DIST_BIAS - (L.pot[u] + w - pot_s));
+      atomicMin((unsigned long long *)&S.bound, (unsigned long long)(~b));
+    }
+    __syncthreads();
+  }
+  // Db (prune only): a center enters a frontier only while r(v) < Db
+  const int64_t Db = !prune ? 0 : mode == 0 ? 0
+                   : S.bound == KEY_NONE ? -DIST_BIAS        // k = 1: no center to reach
+                   : (int64_t)(~S.bound) - DIST_BIAS;
   // target v of this thread and its share g of the frontier (k <= NT: every
   // target gets G = NT / k threads)
   const int G = k <= NT ? NT / k : 1;
@@ -598,8 +640,10 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
                                   ((uint64_t)(int64_t)(int32_t)(hi[x] - 0x80000000u) << 22) +
                                   (1ull << 11) + (uint32_t)u[x]);
       }
-      return best != KEY_NONE && best < atomicMin((unsigned long long *)&lab[v], (unsigned long long)best) &&
-             atomicExch(&stamp[v], t) != t;
+      if (best == KEY_NONE || !(best < atomicMin((unsigned long long *)&lab[v], (unsigned long long)best)))
+        return false;
+      if (prune && (int64_t)(best >> 22) - LAB_BIAS + pot_s - L.pot[v] >= Db) return false;
+      return atomicExch(&stamp[v], t) != t;
     };
     // append the centers whose lanes say so: one LDS atomic per wavefront
     auto append = [&](bool app, int v) {
@@ -626,12 +670,19 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
     relax += (int64_t)nf * k;
     if (nnext == 0) { conv = true; break; }
   }
-  // unpack (hop takes the stamps' place)
+  // unpack (hop takes the stamps' place); pruned: only the centers below
+  // the bound keep their labels
+  const int64_t D = Db > 0 ? Db : 0;
   for (int v = tid; v < k; v += NT) {
     const uint64_t l = lab[v];
-    const bool r = l != KEY_NONE;
-    L.dist[v] = r ? (int64_t)(l >> 22) - LAB_BIAS : DIST_NONE;
-    L.pot2[v] = L.dist[v];
+    const int64_t d = (int64_t)(l >> 22) - LAB_BIAS;
+    const bool r = l != KEY_NONE && (!prune || v == s || d + pot_s - L.pot[v] < Db);
+    L.dist[v] = r ? d : DIST_NONE;
+    if (!prune) L.pot2[v] = L.dist[v];
+    else {
+      const int64_t p2 = r ? d : L.pot[v] - pot_s + D;
+      L.pot2[v] = p2 < POT_FLOOR ? POT_FLOOR : p2;
+    }
     L.hop[v] = r ? (int32_t)((l >> 11) & 0x7ff) : -1;
     L.pred[v] = (r && v != s) ? (int32_t)(l & 0x7ff) : -1;
   }
@@ -650,14 +701,6 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
   return conv;
 }
 
-// Penalty of the j-th unit (j >= 1) beyond the capacity of center s: the
-// constant pen[s], or the j-th value of the center's table (its last value
-// for every later unit).
-__device__ inline int64_t penalty_at(const InstView &I, const Lds &L, int s, int64_t j) {
-  if (!I.pval) return L.pen[s];
-  const int64_t b = I.poff[s], len = I.poff[s + 1] - b;
-  return I.pval[b + (j < len ? j : len) - 1];
-}
 
 // Label of s_in from the center labels (dist, hop) of a search from s.
 // s_in has no out-edges, so the center labels do not depend on its in-edges
@@ -1077,13 +1120,14 @@ __device__ __forceinline__ bool refine(const InstView &I, const Lds &L, Scalars 
     if (S.status != 0) return false;
     sin_from_labels(I, L, s, mode);
   } else {
-    if (!bellman_ford<WLDS>(I, L, S, s, mode)) return false;
+    if (!bellman_ford<WLDS>(I, L, S, s, mode, S.pot_ok != 0)) return false;
     sin_from_labels(I, L, s, mode);
   }
+  const bool complete = !have_labels && !dijkstra && !S.pot_ok;   // unpruned rounds
   const int64_t D = L.dist[k];
   if (D == DIST_NONE || D >= 0) {             // only strictly negative refinements apply
     if (!have_labels) take_potential<WLDS>(I, L, S, s, 0);
-    return !dijkstra;                         // complete labels: Bellman-Ford rounds only
+    return complete;                          // labels of every center describe W
   }
   if (tid == 0) {
     S.pot_ok = 0;                             // W is about to change

@@ -186,3 +186,82 @@ def test_bounded_search_settles_few_centers_when_the_drop_is_small():
     z = np.zeros(k, np.int32)
     _, _, _, _, nset = bounded_search(W, s, pot, 0, z, z, np.ones(k, np.int32), rng)
     assert nset <= 3
+
+
+def pruned_rounds(W, s, pot, mode, load, cap, pen):
+    """The kernel's pruned Bellman-Ford rounds: synchronous rounds from s in
+    which a center whose label dropped enters the next frontier only while
+    its reduced label r = dist + pot[s] - pot[v] is below Db (cycle mode 0,
+    path mode -Pmin).  Returns (dist_sin, pred, labels of the centers below
+    Db, new potentials)."""
+    k = W.shape[0]
+
+    def in_weight(u):
+        if u == s:
+            return None
+        if mode == 0:
+            return None if W[u, s] == pins.KEY_NONE else _delta(W[u, s])
+        return (int(pen[u]) if load[u] >= cap[u] else 0) - int(pen[s])
+
+    if mode == 0:
+        Db = 0
+    else:
+        others = [int(pot[u]) + in_weight(u) - int(pot[s]) for u in range(k) if u != s]
+        Db = -min(others) if others else -(1 << 46)
+    INF = (float("inf"), 0, 0)
+    lab = [INF] * k
+    lab[s] = (0, 0, -1)
+    front = [s]
+    for _ in range(k + 1):
+        new = list(lab)
+        for v in range(k):
+            if v == s:
+                continue
+            for u in front:
+                if W[u, v] == pins.KEY_NONE:
+                    continue
+                c = (lab[u][0] + _delta(W[u, v]), lab[u][1] + 1, u)
+                if c < new[v]:
+                    new[v] = c
+        nxt = [v for v in range(k) if new[v] < lab[v]
+               and new[v][0] + int(pot[s]) - int(pot[v]) < Db]
+        lab = new
+        if not nxt:
+            break
+        front = nxt
+    rel = [v for v in range(k) if lab[v] is not INF and
+           (v == s or lab[v][0] + int(pot[s]) - int(pot[v]) < Db)]
+    cands = [(lab[u][0] + in_weight(u), lab[u][1], u) for u in rel if u != s and in_weight(u) is not None]
+    dist_sin, pred_sin = (None, -1)
+    if cands:
+        c = min(cands)
+        dist_sin, pred_sin = c[0], c[2]
+    pred = {v: lab[v][2] for v in rel}
+    pred[k] = pred_sin
+    D = max(Db, 0)
+    newpot = [lab[v][0] if v in rel else int(pot[v]) - int(pot[s]) + D for v in range(k)]
+    return dist_sin, pred, {v: lab[v][0] for v in rel}, newpot
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("seed", range(150))
+def test_pruned_rounds_match_synchronous_rounds(seed, mode):
+    """Pruned Bellman-Ford (the kernel's rounds while potentials are feasible)
+    gives the oracle's s_in label and path whenever a refinement applies, no
+    negative label otherwise, exact labels below the bound, and potentials
+    feasible where the bounded Dijkstra search's are."""
+    _, k, pot, W, s, load, cap, pen = _case(seed, mode)
+    dist, pred, _ = oracle.refine_search(W, s, mode, load, cap, pen)
+    D_ref = int(dist[k]) if dist[k] != oracle.DIST_NONE else None
+    d, bpred, labels, newpot = pruned_rounds(W, s, pot, mode, load, cap, pen)
+    for v, x in labels.items():
+        if v != s:
+            assert x == dist[v], (seed, mode, v)
+    if D_ref is not None and D_ref < 0:
+        assert d == D_ref, (seed, mode)
+        assert _chain(bpred, k, s) == _chain({v: int(pred[v]) for v in range(k + 1)}, k, s)
+        assert _feasible(W, newpot, skip_s=s), (seed, mode)
+    else:
+        assert d is None or d >= 0, (seed, mode, d, D_ref)
+        assert _feasible(W, newpot), (seed, mode)
+    assert newpot[s] == 0
