@@ -352,6 +352,14 @@ int lbdd_best_transfers(int32_t k, int64_t n, const int32_t *cm, const int32_t *
 int lbdd_best_transfers_noalloc(int32_t k, int64_t n, const int32_t *cm, const int32_t *assign,
                                 const int32_t *rank, uint64_t *W, uint32_t flags, void *hip_stream);
 
+/* A plain streaming read of `bytes` bytes at `src` (device memory, 16-byte
+ * aligned, bytes a multiple of 16) by `blocks` workgroups of 256 threads,
+ * each thread four 16-byte loads in flight: the read bandwidth ceiling that
+ * the cost-matrix scans (Section 3.2, Gamma) are compared with.  The XOR of
+ * the 32-bit words read is XORed into *sink (device, 8 bytes), so every load
+ * is kept.  Asynchronous on `hip_stream`.  Errors: LBDD_E_INVAL, LBDD_E_DEVICE. */
+int lbdd_read_ceiling(const void *src, int64_t bytes, uint64_t *sink, int32_t blocks, void *hip_stream);
+
 /* The tables of many allotments at once (the batched form of the scan above;
  * LBDD_SCAN_REUSE_GROUPING is defined there):
  * item i has k[i] centers (1 <= k[i] <= LBDD_MAX_K) and n[i] >= 0 units, and

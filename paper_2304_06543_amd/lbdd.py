@@ -44,7 +44,7 @@ EXPORTS = ("lbdd_create", "lbdd_solve", "lbdd_solve_iters", "lbdd_solve_batch", 
            "lbdd_tune_best_transfers", "lbdd_create_strict", "lbdd_centers",
            "lbdd_create_penalty_table", "lbdd_road_cm_work_bytes", "lbdd_road_cost_matrix",
            "lbdd_best_transfers_batch_work_bytes", "lbdd_best_transfers_batch",
-           "lbdd_best_transfers_noalloc")
+           "lbdd_best_transfers_noalloc", "lbdd_read_ceiling")
 JOB_QUEUED, JOB_RUNNING, JOB_DONE = 0, 1, 2
 SERVER_STATS = ("submitted", "admitted", "finished", "failed", "kernel_launches",
                 "peak_jobs", "peak_bytes", "bytes_now", "workers")
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
         "lbdd_best_transfers_batch_work_bytes": ([I32, P, P], C.c_size_t),
         "lbdd_best_transfers_batch": ([I32, P, P, P, P, P, P, P, U32, P], C.c_int),
         "lbdd_best_transfers_noalloc": ([I32, I64, P, P, P, P, U32, P], C.c_int),
+        "lbdd_read_ceiling": ([P, I64, P, I32, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -342,6 +343,13 @@ def best_transfers(cm, assign, rank, W=None, work=None, stream=None, reuse_group
                                       SCAN_REUSE_GROUPING if reuse_grouping else 0,
                                       _stream_ptr(stream)))
     return W
+
+
+def read_ceiling(buf, sink, blocks: int, stream=None):
+    """lbdd_read_ceiling over the bytes of the contiguous cuda tensor `buf`;
+    sink is an 8-byte cuda tensor the fold is XORed into."""
+    _check(load().lbdd_read_ceiling(C.c_void_p(buf.data_ptr()), int(buf.numel() * buf.element_size()),
+                                    C.c_void_p(sink.data_ptr()), int(blocks), _stream_ptr(stream)))
 
 
 NOALLOC_SCRATCH_BYTES = 16 << 20
