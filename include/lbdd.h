@@ -214,7 +214,10 @@ int lbdd_snapshot(lbdd_instance *h, int32_t *load, uint64_t *W, int64_t *order);
  *   [22] rounds of those repairs
  *   [23] .. [25] device timer ticks spent in searches in Dijkstra order, in
  *        Bellman-Ford searches, and in potential checks and repairs
- *   [26] device timer frequency in kHz
+ *   [26] sink potentials computed (LBDD_OPT_SINK_EVERY), [27] ticks spent so
+ *   [28] Bellman-Ford searches pruned by feasible potentials (part of the
+ *        searches that are not [18])
+ *   [29] device timer frequency in kHz
  * Synchronises.  Returns the number of counters written (>= 0). */
 int lbdd_stats(lbdd_instance *h, int64_t *out, int32_t count);
 
@@ -234,6 +237,15 @@ int lbdd_stats(lbdd_instance *h, int64_t *out, int32_t count);
  * the instance's stream.  Errors: LBDD_E_INVAL (NULL, unknown option, value
  * out of range), LBDD_E_DEVICE. */
 #define LBDD_OPT_SEARCH_RATIO 1
+/*   LBDD_OPT_SINK_EVERY  int64 in [0, 2^20]: every this many path searches
+ *     (Appendix A), the node potentials are first recomputed as sink
+ *     potentials (minus the cheapest cost of placing one more unit starting
+ *     from each center, q of a center being what its next unit pays), on
+ *     which a path search in Dijkstra order settles little beyond its
+ *     cheapest paths; in between they are checked and repaired on the rows
+ *     of W that changed.  0: never (path searches use the same potentials
+ *     as cycle searches).  New instances start with 8. */
+#define LBDD_OPT_SINK_EVERY 2
 int lbdd_set_option(lbdd_instance *h, int32_t option, int64_t value);
 int lbdd_get_option(lbdd_instance *h, int32_t option, int64_t *value);
 

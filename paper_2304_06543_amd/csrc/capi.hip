@@ -58,7 +58,7 @@ void release(lbdd_instance *h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->st);
   void *ptrs[] = {h->cm, h->smin, h->cap, h->pen, h->assign, h->load, h->members,
-                  h->slot, h->unperm, h->order, h->scalars, h->W, h->Wh, h->best, h->meta, h->thr,
+                  h->slot, h->unperm, h->order, h->scalars, h->W, h->Wh, h->WhT, h->best, h->meta, h->thr,
                   h->poff, h->pval};
   for (void *p : ptrs)
     if (p) (void)hipFreeAsync(p, h->st);
@@ -175,6 +175,7 @@ int create_instance(int32_t k, int64_t n, const int32_t *cm, const int32_t *capa
   if (e == hipSuccess) e = dalloc(&h->scalars, (size_t)lbdd::SC_COUNT, h->st);
   if (e == hipSuccess) e = dalloc(&h->W, (size_t)k * k, h->st);
   if (e == hipSuccess) e = dalloc(&h->Wh, (size_t)k * k, h->st);
+  if (e == hipSuccess) e = dalloc(&h->WhT, (size_t)k * k, h->st);
   if (e == hipSuccess) e = dalloc(&h->best, (size_t)k * k * lbdd::BEST_M, h->st);
   if (e == hipSuccess) e = dalloc(&h->meta, (size_t)k * k, h->st);
   if (e == hipSuccess) e = dalloc(&h->thr, (size_t)k * k, h->st);
@@ -187,7 +188,7 @@ int create_instance(int32_t k, int64_t n, const int32_t *cm, const int32_t *capa
   int32_t *cm_tmp = nullptr, *cm_ext = nullptr, *bad = nullptr, *mx = nullptr;
   int32_t mx_h = 0;                  // read by an async copy: lives until the sync below
   void *work = nullptr;
-  int64_t ratio = 0;                 // read by an async copy: lives until the sync below
+  int64_t opts[2] = {0, 0};          // read by an async copy: lives until the sync below
   int rc = LBDD_OK;
   do {
     if (!(flags & LBDD_CM_DEVICE)) {
@@ -227,9 +228,12 @@ int create_instance(int32_t k, int64_t n, const int32_t *cm, const int32_t *capa
       rc = hip_fail(e, "setup kernels"); break;
     }
     if ((e = lbdd::launch_init_state(h->view(), h->st)) != hipSuccess) { rc = hip_fail(e, "init kernel"); break; }
-    ratio = lbdd::tuned_search_ratio(k);
-    if ((e = hipMemcpyAsync(h->scalars + lbdd::SC_RATIO, &ratio, sizeof ratio, hipMemcpyHostToDevice, h->st)) != hipSuccess) {
-      rc = hip_fail(e, "init search ratio"); break;
+    // the per-instance options, in adjacent scalar slots
+    static_assert(lbdd::SC_SINK_EVERY == lbdd::SC_RATIO + 1, "option slots");
+    opts[0] = lbdd::tuned_search_ratio(k);
+    opts[1] = lbdd::DEFAULT_SINK_EVERY;
+    if ((e = hipMemcpyAsync(h->scalars + lbdd::SC_RATIO, opts, sizeof opts, hipMemcpyHostToDevice, h->st)) != hipSuccess) {
+      rc = hip_fail(e, "init options"); break;
     }
     int32_t bad_h = 0;
     if ((e = hipMemcpyAsync(&bad_h, bad, 4, hipMemcpyDeviceToHost, h->st)) != hipSuccess ||
@@ -279,21 +283,29 @@ int lbdd_centers(lbdd_instance *h, int32_t *k_graph) {
   return LBDD_OK;
 }
 
+// scalar slot of an option, or -1
+static int option_slot(int32_t option) {
+  return option == LBDD_OPT_SEARCH_RATIO ? lbdd::SC_RATIO
+       : option == LBDD_OPT_SINK_EVERY ? lbdd::SC_SINK_EVERY : -1;
+}
+
 int lbdd_set_option(lbdd_instance *h, int32_t option, int64_t value) {
   if (!h) return fail(LBDD_E_INVAL, "NULL handle");
-  if (option != LBDD_OPT_SEARCH_RATIO) return fail(LBDD_E_INVAL, "unknown option %d", option);
-  if (value < lbdd::SEARCH_RATIO_AUTO || value > lbdd::MAX_SEARCH_RATIO)
+  const int slot = option_slot(option);
+  if (slot < 0) return fail(LBDD_E_INVAL, "unknown option %d", option);
+  if (option == LBDD_OPT_SEARCH_RATIO && (value < lbdd::SEARCH_RATIO_AUTO || value > lbdd::MAX_SEARCH_RATIO))
     return fail(LBDD_E_INVAL, "search ratio %lld outside [-1, 2^20]", (long long)value);
-  HIP_TRY(copy_sync(h->scalars + lbdd::SC_RATIO, &value, sizeof value, hipMemcpyHostToDevice, h->st),
-          "set option");
+  if (option == LBDD_OPT_SINK_EVERY && (value < 0 || value > lbdd::MAX_SINK_EVERY))
+    return fail(LBDD_E_INVAL, "sink period %lld outside [0, 2^20]", (long long)value);
+  HIP_TRY(copy_sync(h->scalars + slot, &value, sizeof value, hipMemcpyHostToDevice, h->st), "set option");
   return LBDD_OK;
 }
 
 int lbdd_get_option(lbdd_instance *h, int32_t option, int64_t *value) {
   if (!h || !value) return fail(LBDD_E_INVAL, "NULL argument");
-  if (option != LBDD_OPT_SEARCH_RATIO) return fail(LBDD_E_INVAL, "unknown option %d", option);
-  HIP_TRY(copy_sync(value, h->scalars + lbdd::SC_RATIO, sizeof *value, hipMemcpyDeviceToHost, h->st),
-          "get option");
+  const int slot = option_slot(option);
+  if (slot < 0) return fail(LBDD_E_INVAL, "unknown option %d", option);
+  HIP_TRY(copy_sync(value, h->scalars + slot, sizeof *value, hipMemcpyDeviceToHost, h->st), "get option");
   return LBDD_OK;
 }
 

@@ -30,6 +30,7 @@ struct lbdd_instance {
   int64_t *order = nullptr, *scalars = nullptr;
   uint64_t *W = nullptr;
   uint32_t *Wh = nullptr;
+  uint32_t *WhT = nullptr;
   uint64_t *best = nullptr;
   uint8_t *meta = nullptr;
   uint64_t *thr = nullptr;
@@ -39,7 +40,7 @@ struct lbdd_instance {
   lbdd::InstView view() const {
     lbdd::InstView v;
     v.k = k; v.strict = strict ? 1 : 0; v.n = n; v.cm = cm; v.smin = smin; v.cap = cap; v.pen = pen;
-    v.assign = assign; v.load = load; v.members = members; v.slot = slot; v.W = W; v.Wh = Wh;
+    v.assign = assign; v.load = load; v.members = members; v.slot = slot; v.W = W; v.Wh = Wh; v.WhT = WhT;
     v.best = best; v.meta = meta; v.thr = thr;
     v.scalars = scalars;
     v.poff = poff; v.pval = pval;

@@ -55,6 +55,9 @@ struct InstView {
   uint32_t *Wh;            // [k][k] high words of W (delta + 2^31, all ones = no
                            // transfer): what a search reads, at half the bytes,
                            // while W is in global memory
+  uint32_t *WhT;           // [k][k] the same high words transposed (WhT[v][u] is
+                           // W[u][v]'s), kept in every launch: read by the
+                           // searches toward the penalty sink
   uint64_t *best;          // [k][k][BEST_M] smallest transfer keys of each pair
   uint8_t *meta;           // [k][k] keys held (low 4 bits), every unit held (META_ALL)
   uint64_t *thr;           // [k][k] a joining unit's key changes the list (or its
@@ -79,15 +82,19 @@ enum : int {
   SC_DONE = 1,          // iterations completed
   SC_STATUS = 2,        // 0 ok, else an LBDD_E_* code
   SC_STAT0 = 3,         // first of the counters reported by lbdd_stats
-  SC_NSTATS = 26,
+  SC_NSTATS = 29,
   SC_RATIO = SC_STAT0 + SC_NSTATS,   // search-choice ratio (x16, see refine in solve.hip)
-  SC_COUNT = SC_RATIO + 1
+  SC_SINK_EVERY,                     // path searches per sink-potential computation
+  SC_COUNT
 };
 // Cost of a Bellman-Ford round in Dijkstra steps (x16), or AUTO: the ratio
 // of the measured times of a round and of a step (the default unless tuned).
 constexpr int64_t SEARCH_RATIO_AUTO = -1;
 constexpr int64_t DEFAULT_SEARCH_RATIO = SEARCH_RATIO_AUTO;
 constexpr int64_t MAX_SEARCH_RATIO = 1 << 20;   // Dijkstra whenever it applies
+constexpr int64_t MAX_SINK_EVERY = 1 << 20;
+// Path searches per sink-potential computation unless set per instance.
+constexpr int64_t DEFAULT_SINK_EVERY = 8;
 enum : int {
   ST_CYCLES = 0, ST_PATHS, ST_MOVES, ST_CYC_SEARCH, ST_PATH_SEARCH, ST_BF_ROUNDS,
   ST_ROWS_SCANNED, ST_ITERS, ST_CYC_SKIPPED,
@@ -105,7 +112,10 @@ enum : int {
   ST_REPAIR_ROUNDS,     // rounds of those repairs
   // device timer ticks spent in (thread 0's view): searches in Dijkstra
   // order, Bellman-Ford searches, potential checks and repairs
-  ST_T_DIJKSTRA, ST_T_BF, ST_T_POT
+  ST_T_DIJKSTRA, ST_T_BF, ST_T_POT,
+  ST_SINK,              // sink potentials computed (see sink_potential in solve.hip)
+  ST_T_SINK,            // device timer ticks spent computing them
+  ST_BF_PRUNED          // Bellman-Ford searches pruned by feasible potentials
 };
 
 // one workgroup solves one instance

@@ -55,6 +55,7 @@ __device__ inline int lanes_below(uint64_t mask) {
 struct Lds {
   uint64_t *W;      // [k][k] (LDS copy or the global table)
   uint32_t *wh;     // global high words of W while W is global, else null
+  uint32_t *wt;     // global high words of W transposed (kept in every launch)
   uint64_t *red;    // [k+1] per-target minimum
   int64_t *dist;    // [k+1]
   int32_t *pred;    // [k+1]
@@ -63,6 +64,8 @@ struct Lds {
   int32_t *front1;
   int64_t *pot;     // [k] node potentials (see refine)
   int64_t *pot2;    // [k] candidate potentials from the last search
+  int64_t *potT;    // [k] sink potentials for path searches (see sink_potential)
+  uint32_t *dirty;  // [ceil(k/32)] rows of W changed since potT was last checked
   int32_t *load;    // [k]
   int32_t *cap;     // [k]
   int32_t *pen;     // [k]
@@ -73,10 +76,12 @@ struct Lds {
   uint64_t *wmin;   // [2][NT/64] per-wavefront minima of a refill round
 };
 
-// W[idx] = key, and its high word when W is global
-__device__ inline void set_w(const Lds &L, int64_t idx, uint64_t key) {
+// W[u][w] = key (idx = u k + w), its high word when W is global, and the
+// transposed high word
+__device__ inline void set_w(const Lds &L, int k, int u, int w, int64_t idx, uint64_t key) {
   L.W[idx] = key;
   if (L.wh) L.wh[idx] = (uint32_t)(key >> 32);
+  L.wt[(int64_t)w * k + u] = (uint32_t)(key >> 32);
 }
 
 struct Scalars {
@@ -97,6 +102,11 @@ struct Scalars {
   int32_t step_t;   // running mean of the device ticks per Dijkstra step, x16
   int32_t nsearch;  // searches run (Bellman-Ford or Dijkstra order)
   uint64_t bound;   // pruned Bellman-Ford: biased bound term (see bellman_ford)
+  uint64_t wlo;     // windowed rounds: smallest biased reduced label pending
+  int64_t wdelta;   // windowed rounds: window width (adapted per window)
+  int32_t sink_every;  // path searches per sink-potential computation (0: never)
+  int32_t sink_age;    // path searches since the last one
+  int32_t potT_ok;     // potT is feasible on every edge of W outside the dirty rows
   int32_t jflags[2];  // join_center's result, by iteration parity
 };
 
@@ -106,7 +116,8 @@ struct Scalars {
 // without the k x k table in LDS.
 __host__ __device__ size_t solve_lds_bytes(int k, bool wlds) {
   const size_t K1 = (size_t)k + 1;
-  size_t b = K1 * 8 * 2 + K1 * 4 * 4 + 8 + (size_t)k * 8 * 2 + (size_t)k * 4 * 3 +
+  size_t b = K1 * 8 * 2 + K1 * 4 * 4 + 8 + (size_t)k * 8 * 3 + ((size_t)k + 31) / 32 * 4 + 8 +
+             (size_t)k * 4 * 3 +
              K1 * 4 * 3 + K1 * 4 + 8 + 2 * (SOLVE_THREADS / 64) * 8;
   if (wlds) b += (size_t)k * k * 8;
   return b;
@@ -194,7 +205,7 @@ __device__ __forceinline__ void join_one(const InstView &I, const Lds &L, int x,
   I.meta[idx] = (uint8_t)(c2 | (all2 ? META_ALL : 0));
   I.thr[idx] = list_threshold(a, c2, all2);
   if (a[0] < L.W[idx]) {
-    set_w(L, idx, a[0]);
+    set_w(L, k, v, w, idx, a[0]);
     changed = 1;
     breaks |= L.pot[v] + delta < L.pot[w];
   }
@@ -240,7 +251,7 @@ __device__ __forceinline__ void leave_one(const InstView &I, const Lds &L, int x
   list_store(I.best + idx * BEST_M, a);
   I.meta[idx] = (uint8_t)((c - 1) | (meta & META_ALL));
   I.thr[idx] = list_threshold(a, c - 1, meta & META_ALL);
-  set_w(L, idx, a[0]);                         // stale if unknown; refill sets it
+  set_w(L, k, u, w, idx, a[0]);                // stale if unknown; refill sets it
 }
 
 // The moved units of an applied refinement leave their old centers' lists,
@@ -320,7 +331,7 @@ __device__ __forceinline__ void refill_column(const InstView &I, const Lds &L, S
     for (int j = 0; j < BEST_M; ++j) c += out[j] != KEY_NONE;
     I.meta[idx] = (uint8_t)(c | (m <= BEST_M ? META_ALL : 0));
     I.thr[idx] = list_threshold(out, c, m <= BEST_M);
-    set_w(L, idx, out[0]);
+    set_w(L, k, u, w, idx, out[0]);
     S.stats[ST_ROWS_SCANNED] += m;
     S.stats[ST_REFILLS] += 1;
   }
@@ -401,6 +412,63 @@ constexpr int64_t REP_BIAS = 1ll << 62;   // repair labels lie in (-2^62, 0]
 // units) can sink this low (one with an edge into s stays within 2^30 of it); raising such a center's potential keeps its in-edges feasible, whose
 // sources have out-edges and so potentials far above the floor.
 constexpr int64_t POT_FLOOR = -(1ll << 42);
+// Repair rounds on the potential P from the tails of failed edges already in
+// the frontier list 1 (S.nfront[1] of them, round stamp 1, every label at
+// REP_BIAS, i.e. 0): on convergence P += lab, shifted so that P[norm] is
+// unchanged plus its own label when norm >= 0.  Returns false without
+// convergence (then P is unchanged).
+template <bool WLDS>
+__device__ __forceinline__ bool repair_rounds(const InstView &I, const Lds &L, Scalars &S, int64_t *P,
+                                              int norm) {
+  const int k = I.k;
+  const int tid = threadIdx.x;
+  constexpr int WS = WLDS ? 2 : 1;
+  const uint32_t *Whi = WLDS ? reinterpret_cast<const uint32_t *>(L.W) + 1 : L.wh;
+  uint64_t *lab = L.red;
+  int32_t *stamp = L.trow;
+  bool conv = false;
+  int64_t rounds = 0;
+  for (int t = 1; t <= k + 1; ++t) {
+    // round t relaxes out of the frontier of size nfront[t % 3] in list t & 1
+    // (see bellman_ford)
+    const int nf = S.nfront[t % 3];
+    const int32_t *F = (t & 1) ? L.front1 : L.front0;
+    int32_t *Fn = (t & 1) ? L.front0 : L.front1;
+    int32_t *cnt_next = &S.nfront[(t + 1) % 3];
+    if (tid == 0) S.nfront[(t + 2) % 3] = 0;
+    for (int64_t x = tid; x < (int64_t)nf * k; x += NT) {
+      const int j = (int)(x / k), v = (int)(x - (int64_t)j * k);
+      const int u = F[j];
+      if (u == v) continue;
+      const uint32_t hi = Whi[WS * ((int64_t)u * k + v)];
+      if (hi == 0xffffffffu) continue;
+      const int64_t cand = (int64_t)(lab[u] - (uint64_t)REP_BIAS) + (int64_t)(int32_t)(hi ^ 0x80000000u) +
+                           P[u] - P[v];
+      if (cand >= 0) continue;
+      const uint64_t c = (uint64_t)(cand + REP_BIAS);
+      if (c < atomicMin((unsigned long long *)&lab[v], (unsigned long long)c) &&
+          atomicExch(&stamp[v], t + 1) != t + 1)
+        Fn[atomicAdd(cnt_next, 1)] = v;
+    }
+    __syncthreads();
+    ++rounds;
+    if (*cnt_next == 0) { conv = true; break; }
+  }
+  if (conv) {
+    const int64_t shift = norm >= 0 ? (int64_t)(lab[norm] - (uint64_t)REP_BIAS) : 0;
+    for (int u = tid; u < k; u += NT) {
+      const int64_t p = P[u] + (int64_t)(lab[u] - (uint64_t)REP_BIAS) - shift;
+      P[u] = p < POT_FLOOR ? POT_FLOOR : p;
+    }
+  }
+  if (tid == 0) {
+    S.stats[ST_POT_REPAIRS] += 1;
+    S.stats[ST_REPAIR_ROUNDS] += rounds;
+  }
+  __syncthreads();
+  return conv;
+}
+
 template <bool WLDS>
 __device__ __forceinline__ void take_potential(const InstView &I, const Lds &L, Scalars &S, int s,
                                                int nmov) {
@@ -440,55 +508,54 @@ __device__ __forceinline__ void take_potential(const InstView &I, const Lds &L, 
     }
   unknown = __syncthreads_or(unknown);
   bool ok = !unknown;
-  const int nbad = S.nfront[1];
-  if (ok && nbad > 0) {
-    // repair rounds: round t relaxes out of the frontier of size nfront[t % 3]
-    // in list t & 1 (see bellman_ford)
-    bool conv = false;
-    int64_t rounds = 0;
-    for (int t = 1; t <= k + 1; ++t) {
-      const int nf = S.nfront[t % 3];
-      const int32_t *F = (t & 1) ? L.front1 : L.front0;
-      int32_t *Fn = (t & 1) ? L.front0 : L.front1;
-      int32_t *cnt_next = &S.nfront[(t + 1) % 3];
-      if (tid == 0) S.nfront[(t + 2) % 3] = 0;
-      for (int64_t x = tid; x < (int64_t)nf * k; x += NT) {
-        const int j = (int)(x / k), v = (int)(x - (int64_t)j * k);
-        const int u = F[j];
-        if (u == v) continue;
-        const uint32_t hi = Whi[WS * ((int64_t)u * k + v)];
-        if (hi == 0xffffffffu) continue;
-        const int64_t cand = (int64_t)(lab[u] - (uint64_t)REP_BIAS) + (int64_t)(int32_t)(hi ^ 0x80000000u) +
-                             L.pot2[u] - L.pot2[v];
-        if (cand >= 0) continue;
-        const uint64_t c = (uint64_t)(cand + REP_BIAS);
-        if (c < atomicMin((unsigned long long *)&lab[v], (unsigned long long)c) &&
-            atomicExch(&stamp[v], t + 1) != t + 1)
-          Fn[atomicAdd(cnt_next, 1)] = v;
-      }
-      __syncthreads();
-      ++rounds;
-      if (*cnt_next == 0) { conv = true; break; }
-    }
-    ok = conv;
-    if (ok) {
-      const int64_t shift = L.pot2[s] + (int64_t)(lab[s] - (uint64_t)REP_BIAS);
-      for (int u = tid; u < k; u += NT) {
-        const int64_t p = L.pot2[u] + (int64_t)(lab[u] - (uint64_t)REP_BIAS) - shift;
-        L.pot2[u] = p < POT_FLOOR ? POT_FLOOR : p;
-      }
-    }
-    if (tid == 0) {
-      S.stats[ST_POT_REPAIRS] += 1;
-      S.stats[ST_REPAIR_ROUNDS] += rounds;
-    }
-  }
-  __syncthreads();
+  if (ok && S.nfront[1] > 0) ok = repair_rounds<WLDS>(I, L, S, L.pot2, s);
   if (ok)
     for (int u = tid; u < k; u += NT) L.pot[u] = L.pot2[u];
   if (tid == 0) {
     S.pot_ok = ok;
     if (ok && nmov > 0) S.stats[ST_POT_KEPT] += 1;
+    S.stats[ST_T_POT] += now() - t_start;
+  }
+  __syncthreads();
+}
+
+// The sink potentials potT before a path search: the rows of W that changed
+// since potT was last checked (joins, moves) are checked, the tails of their
+// failed edges start the repair rounds, and the rows are clean again.  An
+// unconverged repair leaves potT invalid (it is computed afresh).
+template <bool WLDS>
+__device__ __forceinline__ void refresh_sink(const InstView &I, const Lds &L, Scalars &S) {
+  const int k = I.k;
+  const int tid = threadIdx.x;
+  constexpr int WS = WLDS ? 2 : 1;
+  const uint32_t *Whi = WLDS ? reinterpret_cast<const uint32_t *>(L.W) + 1 : L.wh;
+  uint64_t *lab = L.red;
+  int32_t *stamp = L.trow;
+  const int64_t t_start = tid == 0 ? now() : 0;
+  for (int u = tid; u < k; u += NT) {
+    lab[u] = (uint64_t)REP_BIAS;
+    stamp[u] = 0;
+  }
+  if (tid == 0) { S.nfront[0] = S.nfront[1] = S.nfront[2] = 0; S.nrefill = 0; }
+  __syncthreads();
+  for (int u = tid; u < k; u += NT)
+    if ((L.dirty[u >> 5] >> (u & 31)) & 1u) L.mrow[atomicAdd(&S.nrefill, 1)] = u;
+  __syncthreads();
+  const int nd = S.nrefill;
+  for (int64_t t = tid; t < (int64_t)nd * k; t += NT) {
+    const int j = (int)(t / k), v = (int)(t - (int64_t)j * k);
+    const int u = L.mrow[j];
+    if (u == v) continue;
+    const uint32_t hi = Whi[WS * ((int64_t)u * k + v)];
+    if (hi == 0xffffffffu) continue;
+    if (L.potT[u] + (int64_t)(int32_t)(hi ^ 0x80000000u) < L.potT[v] && atomicExch(&stamp[u], 1) != 1)
+      L.front1[atomicAdd(&S.nfront[1], 1)] = u;
+  }
+  __syncthreads();
+  const bool ok = S.nfront[1] == 0 || repair_rounds<WLDS>(I, L, S, L.potT, -1);
+  for (int i = tid; i < (k + 31) / 32; i += NT) L.dirty[i] = 0;
+  if (tid == 0) {
+    if (!ok) S.potT_ok = 0;
     S.stats[ST_T_POT] += now() - t_start;
   }
   __syncthreads();
@@ -509,6 +576,69 @@ __device__ inline int64_t penalty_at(const InstView &I, const Lds &L, int s, int
   if (!I.pval) return L.pen[s];
   const int64_t b = I.poff[s], len = I.poff[s + 1] - b;
   return I.pval[b + (j < len ? j : len) - 1];
+}
+
+// Sink potentials: the node potentials -sigma, sigma(v) the cheapest way to
+// give one more unit to some center starting from v: sigma(v) = min(q(v),
+// min over w of W[v][w] + sigma(w)), q(v) what one more unit at v pays (0
+// while v has room).  These are the shortest distances to a sink that every
+// center joins by an edge of weight q(v); W has no negative cycle (Lemmas 1
+// and 2), so they exist, and -sigma is feasible on every edge of W.  A path
+// search (Appendix A) in Dijkstra order on them settles little beyond the
+// centers of its cheapest paths: its bound term P(u) = q(u) - sigma(u) +
+// sigma(s) - q(s) takes its smallest value, sigma(s) - q(s), on the center
+// that ends a cheapest path, which is also the best candidate.  Computed as
+// rounds from the sink over the reversed edges (the transposed high words),
+// every center in the first frontier; after a round with no change the
+// potentials replace potT (every row clean).  Without convergence (a
+// negative cycle) nothing changes and the status records the failed
+// invariant.
+template <bool WLDS>
+__device__ __forceinline__ void sink_potential(const InstView &I, const Lds &L, Scalars &S) {
+  const int k = I.k;
+  const int tid = threadIdx.x;
+  const int64_t t_start = tid == 0 ? now() : 0;
+  uint64_t *lab = L.red;                         // sigma + DIST_BIAS
+  int32_t *stamp = L.trow;                       // last round whose frontier took the center
+  for (int v = tid; v < k; v += NT) {
+    const int64_t q = L.load[v] >= L.cap[v] ? penalty_at(I, L, v, (int64_t)L.load[v] - L.cap[v] + 1) : 0;
+    lab[v] = (uint64_t)(q + DIST_BIAS);
+    stamp[v] = 1;
+    L.front1[v] = v;
+  }
+  if (tid == 0) { S.nfront[0] = 0; S.nfront[1] = k; S.nfront[2] = 0; }
+  __syncthreads();
+  bool conv = false;
+  for (int t = 1; t <= k + 1; ++t) {
+    const int nf = S.nfront[t % 3];
+    const int32_t *F = (t & 1) ? L.front1 : L.front0;
+    int32_t *Fn = (t & 1) ? L.front0 : L.front1;
+    int32_t *cnt_next = &S.nfront[(t + 1) % 3];
+    if (tid == 0) S.nfront[(t + 2) % 3] = 0;
+    for (int64_t x = tid; x < (int64_t)nf * k; x += NT) {
+      const int j = (int)(x / k), v = (int)(x - (int64_t)j * k);
+      const int w = F[j];
+      if (v == w) continue;
+      const uint32_t hi = L.wt[(int64_t)w * k + v];   // W[v][w]
+      if (hi == 0xffffffffu) continue;
+      const uint64_t c = lab[w] + (uint64_t)(int64_t)(int32_t)(hi ^ 0x80000000u);
+      if (c < atomicMin((unsigned long long *)&lab[v], (unsigned long long)c) &&
+          atomicExch(&stamp[v], t + 1) != t + 1)
+        Fn[atomicAdd(cnt_next, 1)] = v;
+    }
+    __syncthreads();
+    if (*cnt_next == 0) { conv = true; break; }
+  }
+  if (conv)
+    for (int v = tid; v < k; v += NT) L.potT[v] = DIST_BIAS - (int64_t)lab[v];
+  for (int i = tid; i < (k + 31) / 32; i += NT) L.dirty[i] = 0;
+  if (tid == 0) {
+    S.potT_ok = conv;
+    if (!conv) S.status = -5;                    // LBDD_E_INTERNAL: negative cycle
+    S.stats[ST_SINK] += 1;
+    S.stats[ST_T_SINK] += now() - t_start;
+  }
+  __syncthreads();
 }
 
 // Label of a center during a search, packed so that one unsigned min orders
@@ -600,7 +730,106 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
   const int tg = k <= NT ? tid / k : 0;
   int64_t rounds = 0, relax = 0;
   bool conv = false;
-  for (int t = 1; t <= k + 1; ++t) {
+  if (!WLDS && prune) {
+    // Windowed rounds (the table in global memory, potentials feasible):
+    // the centers whose label dropped since they were last relaxed are
+    // pending; each window takes the smallest pending reduced label lo and
+    // relaxes, round after round, only the pending centers below lo + width,
+    // until none is left there.  Reduced weights beyond the first hop are
+    // non-negative, so a center is mostly relaxed once, with its final
+    // label; the labels reach the same least fixpoint as in any order.  The
+    // search ends when no pending center is below the bound Db.
+    int32_t *pend = L.mrow;                     // [k] 1: pending
+    for (int v = tid; v < k; v += NT) pend[v] = v == s;
+    __syncthreads();
+    const int64_t cap_rounds = 4 * (int64_t)k + 64;   // a safety net; never reached without a
+                                                      // negative cycle off s
+    conv = true;
+    for (bool first = true;; first = false) {
+      if (tid == 0) S.wlo = KEY_NONE;
+      __syncthreads();
+      for (int v = tid; v < k; v += NT)
+        if (pend[v]) {
+          const int64_t r = (int64_t)(lab[v] >> 22) - LAB_BIAS + pot_s - L.pot[v];
+          atomicMin((unsigned long long *)&S.wlo, (unsigned long long)(r + DIST_BIAS));
+        }
+      __syncthreads();
+      const uint64_t wl = S.wlo;
+      if (wl == KEY_NONE) break;
+      const int64_t lo = (int64_t)wl - DIST_BIAS;
+      if (lo >= Db && !first) break;             // the first window relaxes s itself
+      const int64_t hi = lo + S.wdelta;
+      int nf_first = -1;
+      for (;;) {
+        __syncthreads();                          // every thread read S.wlo / S.nfront
+        if (tid == 0) S.nfront[0] = 0;
+        __syncthreads();
+        // the pending centers of the window become the frontier, with
+        // their label bases and row offsets (see the rounds below)
+        for (int v = tid; v < k; v += NT)
+          if (pend[v]) {
+            const uint64_t l = lab[v];
+            const int64_t r = (int64_t)(l >> 22) - LAB_BIAS + pot_s - L.pot[v];
+            if (r < hi) {
+              pend[v] = 0;
+              const int j = atomicAdd(&S.nfront[0], 1);
+              L.front1[j] = v;
+              L.dist[j] = (int64_t)((l & ~(uint64_t)0x7ff) + (1ull << 11) + (uint32_t)v);
+              L.pred[j] = v * k;
+            }
+          }
+        __syncthreads();
+        const int nf = S.nfront[0];
+        if (nf == 0) break;
+        if (nf_first < 0) nf_first = nf;
+        const uint64_t *FB = reinterpret_cast<const uint64_t *>(L.dist);
+        constexpr int B = 4;
+        const int G = k <= NT ? NT / k : 1;
+        auto relax_pend = [&](int v, int j0) {
+          uint64_t best = KEY_NONE;
+          for (int j = j0; j < nf; j += B * G) {
+            uint64_t bs[B];
+            uint32_t hw[B];
+            bool ok[B];
+#pragma unroll
+            for (int x = 0; x < B; ++x) {
+              const int jj = j + x * G;
+              ok[x] = jj < nf;
+              const int idx = ok[x] ? jj : j;
+              bs[x] = FB[idx];
+              hw[x] = Whi[(uint32_t)(L.pred[idx] + v)];
+            }
+#pragma unroll
+            for (int x = 0; x < B; ++x) {
+              const uint64_t c = bs[x] + ((uint64_t)(int64_t)(int32_t)(hw[x] ^ 0x80000000u) << 22);
+              best = (ok[x] && hw[x] != 0xffffffffu && c < best) ? c : best;
+            }
+          }
+          if (best != KEY_NONE && best < atomicMin((unsigned long long *)&lab[v], (unsigned long long)best) &&
+              (int64_t)(best >> 22) - LAB_BIAS + pot_s - L.pot[v] < Db)
+            pend[v] = 1;
+        };
+        if (k <= NT) {
+          const int tv = tid % k, tg = tid / k;
+          if (tg < G && tv != s) relax_pend(tv, tg);
+        } else {
+          for (int v = tid; v < k; v += NT)
+            if (v != s) relax_pend(v, 0);
+        }
+        rounds += 1;
+        relax += (int64_t)nf * k;
+        if (rounds > cap_rounds) break;
+      }
+      if (rounds > cap_rounds) { conv = false; break; }
+      // aim at a few dozen centers per window
+      if (tid == 0) {
+        if (nf_first < 16) S.wdelta = S.wdelta < (1ll << 40) ? S.wdelta * 2 : S.wdelta;
+        else if (nf_first > 64) S.wdelta = S.wdelta > 1 ? S.wdelta / 2 : 1;
+      }
+    }
+    __syncthreads();
+  }
+  for (int t = 1; t <= k + 1 && !(!WLDS && prune); ++t) {
     // round t relaxes out of the frontier of size nfront[t % 3] in list t & 1,
     // appends to nfront[(t + 1) % 3] and list (t + 1) & 1, and clears
     // nfront[(t + 2) % 3]: that counter was last read before the previous
@@ -614,9 +843,43 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
     // true when v's label dropped and v is not yet in the next frontier
     // (several threads of a target may lower it; the stamp admits one).
     constexpr int B = 4;
+    if (!WLDS) {
+      // table in global memory: every frontier entry's label base (label
+      // without its predecessor, plus one edge, with the entry as
+      // predecessor) and row offset are formed once, so a relaxation is a
+      // load, a shifted add and a minimum (dist and pred are free until the
+      // labels are unpacked)
+      for (int j = tid; j < nf; j += NT) {
+        const int u = F[j];
+        L.dist[j] = (int64_t)((lab[u] & ~(uint64_t)0x7ff) + (1ull << 11) + (uint32_t)u);
+        L.pred[j] = u * k;
+      }
+      __syncthreads();
+    }
+    const uint64_t *FB = reinterpret_cast<const uint64_t *>(L.dist);
     auto relax_target = [&](int v, int j0) -> bool {
       uint64_t best = KEY_NONE;
-      for (int j = j0; j < nf; j += B * G) {
+      if (!WLDS) {
+        for (int j = j0; j < nf; j += B * G) {
+          uint64_t bs[B];
+          uint32_t hi[B];
+          bool ok[B];
+#pragma unroll
+          for (int x = 0; x < B; ++x) {
+            const int jj = j + x * G;
+            ok[x] = jj < nf;
+            const int idx = ok[x] ? jj : j;
+            bs[x] = FB[idx];
+            hi[x] = Whi[(uint32_t)(L.pred[idx] + v)];
+          }
+#pragma unroll
+          for (int x = 0; x < B; ++x) {
+            const uint64_t c = bs[x] + ((uint64_t)(int64_t)(int32_t)(hi[x] ^ 0x80000000u) << 22);
+            best = (ok[x] && hi[x] != 0xffffffffu && c < best) ? c : best;
+          }
+        }
+      }
+      for (int j = j0; WLDS && j < nf; j += B * G) {
         int32_t u[B], off[B];
         bool ok[B];
 #pragma unroll
@@ -689,6 +952,7 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
   if (tid == 0) {
     S.stats[ST_BF_ROUNDS] += rounds;
     S.stats[ST_RELAX] += relax;
+    if (prune) S.stats[ST_BF_PRUNED] += 1;
     S.depth[mode] += ((int32_t)rounds * 16 - S.depth[mode]) / 8;
     const int64_t spent = now() - t_start;
     S.stats[ST_T_BF] += spent;
@@ -1084,9 +1348,15 @@ __device__ __forceinline__ void dijkstra_waves(const InstView &I, const Lds &L, 
 // Bellman-Ford rounds.
 template <bool WLDS>
 __device__ __forceinline__ bool refine(const InstView &I, const Lds &L, Scalars &S, int s, int mode,
-                                       bool have_labels) {
+                                       bool have_labels, bool use_t) {
   const int k = I.k;
   const int tid = threadIdx.x;
+  // the potentials the search runs on: the sink potentials (path searches,
+  // use_t) or pot; the search reads them through LS
+  Lds LS = L;
+  if (use_t) LS.pot = L.potT;
+  const bool a_ok = S.pot_ok != 0;
+  const bool pok = use_t ? S.potT_ok != 0 : a_ok;
   // cost model: a Bellman-Ford search takes `depth` rounds and one in
   // Dijkstra order `settled` steps (running means per mode, x16), and a round
   // costs `ratio` steps (x16): a fixed value, or by default the ratio of the
@@ -1105,7 +1375,7 @@ __device__ __forceinline__ bool refine(const InstView &I, const Lds &L, Scalars 
     prefer = (int64_t)S.depth[mode] * ratio > 16 * (int64_t)S.settled[mode];
     if ((S.nsearch & 63) == 63) prefer = !prefer;
   }
-  const bool dijkstra = !have_labels && S.pot_ok && k <= DJ_MAX_K && prefer;
+  const bool dijkstra = !have_labels && pok && k <= DJ_MAX_K && prefer;
   if (tid == 0) {
     S.stats[mode == 0 ? ST_CYC_SEARCH : ST_PATH_SEARCH] += 1;
     if (have_labels) S.stats[ST_PATH_DERIVED] += 1;
@@ -1114,19 +1384,20 @@ __device__ __forceinline__ bool refine(const InstView &I, const Lds &L, Scalars 
   if (have_labels) {
     sin_from_labels(I, L, s, 1);
   } else if (dijkstra) {
-    if (k <= 64) dijkstra_bounded<WLDS, 1>(I, L, S, s, mode);
-    else if (k <= 128) dijkstra_bounded<WLDS, 2>(I, L, S, s, mode);
-    else dijkstra_waves<WLDS>(I, L, S, s, mode);
+    if (k <= 64) dijkstra_bounded<WLDS, 1>(I, LS, S, s, mode);
+    else if (k <= 128) dijkstra_bounded<WLDS, 2>(I, LS, S, s, mode);
+    else dijkstra_waves<WLDS>(I, LS, S, s, mode);
     if (S.status != 0) return false;
     sin_from_labels(I, L, s, mode);
   } else {
-    if (!bellman_ford<WLDS>(I, L, S, s, mode, S.pot_ok != 0)) return false;
+    if (!bellman_ford<WLDS>(I, LS, S, s, mode, pok)) return false;
     sin_from_labels(I, L, s, mode);
   }
-  const bool complete = !have_labels && !dijkstra && !S.pot_ok;   // unpruned rounds
+  const bool complete = !have_labels && !dijkstra && !pok;   // unpruned rounds
   const int64_t D = L.dist[k];
   if (D == DIST_NONE || D >= 0) {             // only strictly negative refinements apply
-    if (!have_labels) take_potential<WLDS>(I, L, S, s, 0);
+    // nothing moved; a search on the sink potentials leaves pot as it was
+    if (!have_labels && !use_t) take_potential<WLDS>(I, L, S, s, 0);
     return complete;                          // labels of every center describe W
   }
   if (tid == 0) {
@@ -1191,12 +1462,30 @@ __device__ __forceinline__ bool refine(const InstView &I, const Lds &L, Scalars 
     for (int64_t t = tid; t < (int64_t)2 * nmov * k; t += NT) {
       const int j = (int)(t / k), w = (int)(t - (int64_t)j * k);
       const int u = (j & 1) ? L.mto[j >> 1] : L.mfrom[j >> 1];
-      set_w(L, (int64_t)u * k + w, strict_entry(I, L, u, w));
+      set_w(L, k, u, w, (int64_t)u * k + w, strict_entry(I, L, u, w));
     }
   }
   if (tid == 0) S.stats[ST_T_RESCAN] += now() - t0;
   __syncthreads();
-  if (S.status == 0) take_potential<WLDS>(I, L, S, s, nmov);
+  if (S.status == 0) {
+    if (!use_t) {
+      take_potential<WLDS>(I, L, S, s, nmov);
+    } else if (a_ok) {
+      // the search ran on the sink potentials: pot itself is checked (and
+      // repaired) on the changed rows
+      for (int u = tid; u < k; u += NT) L.pot2[u] = L.pot[u];
+      __syncthreads();
+      take_potential<WLDS>(I, L, S, s, nmov);
+    }
+  }
+  // the moves changed the rows of their centers: potT checks them later
+  if (S.sink_every > 0) {
+    for (int e = tid; e < nmov; e += NT) {
+      atomicOr(&L.dirty[L.mfrom[e] >> 5], 1u << (L.mfrom[e] & 31));
+      atomicOr(&L.dirty[L.mto[e] >> 5], 1u << (L.mto[e] & 31));
+    }
+    __syncthreads();
+  }
   return false;
 }
 
@@ -1233,6 +1522,7 @@ __device__ __forceinline__ Lds carve_lds(const InstView &I, unsigned char *lds) 
   if (WLDS) { L.W = reinterpret_cast<uint64_t *>(p); p += (size_t)k * k * 8; }
   else L.W = I.W;
   L.wh = WLDS ? nullptr : I.Wh;
+  L.wt = I.WhT;
   L.red = reinterpret_cast<uint64_t *>(p); p += (size_t)K1 * 8;
   L.dist = reinterpret_cast<int64_t *>(p); p += (size_t)K1 * 8;
   L.pred = reinterpret_cast<int32_t *>(p); p += (size_t)K1 * 4;
@@ -1242,6 +1532,9 @@ __device__ __forceinline__ Lds carve_lds(const InstView &I, unsigned char *lds) 
   p = lds + (((p - lds) + 7) & ~(ptrdiff_t)7);   // offsets keep the LDS address space
   L.pot = reinterpret_cast<int64_t *>(p); p += (size_t)k * 8;
   L.pot2 = reinterpret_cast<int64_t *>(p); p += (size_t)k * 8;
+  L.potT = reinterpret_cast<int64_t *>(p); p += (size_t)k * 8;
+  L.dirty = reinterpret_cast<uint32_t *>(p); p += ((size_t)k + 31) / 32 * 4;
+  p = lds + (((p - lds) + 7) & ~(ptrdiff_t)7);
   L.load = reinterpret_cast<int32_t *>(p); p += (size_t)k * 4;
   L.cap = reinterpret_cast<int32_t *>(p); p += (size_t)k * 4;
   L.pen = reinterpret_cast<int32_t *>(p); p += (size_t)k * 4;
@@ -1267,6 +1560,7 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
   else   // a launch that kept W in LDS left the high words behind
     for (int64_t i = tid; i < (int64_t)k * k; i += NT) L.wh[i] = (uint32_t)(I.W[i] >> 32);
   for (int i = tid; i < k; i += NT) L.pot[i] = 0;
+  for (int i = tid; i < (k + 31) / 32; i += NT) L.dirty[i] = 0;
   for (int i = tid; i < k; i += NT) { L.load[i] = I.load[i]; L.cap[i] = I.cap[i]; L.pen[i] = I.pen[i]; }
   if (tid == 0) {
     // the potential is not kept between launches: the first search rebuilds it
@@ -1278,6 +1572,10 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
     S.nsearch = 0;
     S.jflags[0] = S.jflags[1] = 0;
     S.ratio = (int32_t)min(max(I.scalars[SC_RATIO], SEARCH_RATIO_AUTO), MAX_SEARCH_RATIO);
+    S.sink_every = (int32_t)min(max(I.scalars[SC_SINK_EVERY], (int64_t)0), (int64_t)MAX_SINK_EVERY);
+    S.sink_age = 0;
+    S.potT_ok = 0;
+    S.wdelta = 64;
     S.obj = I.scalars[SC_OBJECTIVE];
     S.status = (int32_t)I.scalars[SC_STATUS];
     for (int j = 0; j < SC_NSTATS; ++j) S.stats[j] = I.scalars[SC_STAT0 + j];
@@ -1338,9 +1636,10 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
         S.obj += (int64_t)row[s] + (vac ? 0 : penalty_at(I, L, s, (int64_t)ld - L.cap[s] + 1));
       }
       const int ins = join_center(I, L, S, (int)r, s, (int)(r & 1));   // contains a barrier
+      if ((ins & 1) && S.sink_every > 0 && tid == 0) atomicOr(&L.dirty[s >> 5], 1u << (s & 31));
       if (I.strict && L.load[s] == L.cap[s]) {
         // s has just become full: its dummy transfers are gone
-        for (int v = tid; v < k; v += NT) set_w(L, (int64_t)s * k + v, strict_entry(I, L, s, v));
+        for (int v = tid; v < k; v += NT) set_w(L, k, s, v, (int64_t)s * k + v, strict_entry(I, L, s, v));
         __syncthreads();
       }
       const int64_t t1 = timed ? now() : 0;
@@ -1349,12 +1648,27 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
       // potentials no longer certify that W has none.
       const bool search = (ins & 1) && (!S.pot_ok || (ins & 2));
       bool labels = false;                        // LDS labels describe the current W
-      if (search) labels = refine<WLDS>(I, L, S, s, 0, false);
+      if (search) labels = refine<WLDS>(I, L, S, s, 0, false, false);
       else if (tid == 0) S.stats[ST_CYC_SKIPPED] += 1;
       __syncthreads();
       const int64_t t2 = timed ? now() : 0;
       if (S.status != 0) break;
-      if (!S.vacant) refine<WLDS>(I, L, S, s, 1, labels && S.status == 0);
+      if (!S.vacant) {
+        // path searches run on the sink potentials: checked on the rows
+        // changed since, or computed afresh every sink_every-th path search
+        // (and whenever a check cannot repair them)
+        bool use_t = false;
+        if (S.sink_every > 0 && S.status == 0) {
+          const bool due = !S.potT_ok || S.sink_age + 1 >= S.sink_every;   // the same in every thread
+          __syncthreads();                      // read before thread 0 writes it
+          if (!due) refresh_sink<WLDS>(I, L, S);
+          if (due || !S.potT_ok) sink_potential<WLDS>(I, L, S);
+          if (threadIdx.x == 0) S.sink_age = due ? 0 : S.sink_age + 1;
+          __syncthreads();
+          use_t = S.potT_ok != 0;
+        }
+        if (S.status == 0) refine<WLDS>(I, L, S, s, 1, labels, use_t);
+      }
       __syncthreads();
       if (timed) {
         const int64_t t3 = now();
@@ -1427,6 +1741,7 @@ __global__ void init_state_kernel(InstView I) {
     const uint64_t w0 = (I.strict && u != v && I.cap[u] > 0) ? DUMMY_KEY : KEY_NONE;
     I.W[i] = w0;
     I.Wh[i] = (uint32_t)(w0 >> 32);
+    I.WhT[(int64_t)v * I.k + u] = (uint32_t)(w0 >> 32);
     I.meta[i] = META_ALL;                       // empty center: every unit (none) held
     I.thr[i] = KEY_NONE;                        // ... so every joining unit enters
   }

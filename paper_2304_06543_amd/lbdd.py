@@ -27,7 +27,8 @@ STATS = ("cycles", "paths", "moves", "cycle_searches", "path_searches", "bf_roun
          "ticks_allot", "ticks_cycle", "ticks_path", "ticks_rescan", "refills",
          "tick_first", "tick_last", "relaxations", "paths_derived", "dijkstra",
          "potentials_kept", "dijkstra_settled", "potential_repairs", "repair_rounds",
-         "ticks_dijkstra", "ticks_bf", "ticks_potentials", "timer_khz")
+         "ticks_dijkstra", "ticks_bf", "ticks_potentials", "sink_potentials", "ticks_sink",
+         "bf_pruned", "timer_khz")
 
 # search ratios lbdd_tune_search times, in order: measured during the solve,
 # always Bellman-Ford, a fixed 4 steps per round, Dijkstra whenever allowed
@@ -130,6 +131,7 @@ def _host_i32(a) -> np.ndarray:
 
 
 OPT_SEARCH_RATIO = 1
+OPT_SINK_EVERY = 2
 
 
 def _create_args(cm, capacity, penalty):

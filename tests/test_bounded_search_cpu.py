@@ -265,3 +265,72 @@ def test_pruned_rounds_match_synchronous_rounds(seed, mode):
         assert d is None or d >= 0, (seed, mode, d, D_ref)
         assert _feasible(W, newpot), (seed, mode)
     assert newpot[s] == 0
+
+
+def windowed_rounds(W, s, pot, mode, load, cap, pen, width):
+    """The kernel's windowed rounds: centers whose label dropped are pending;
+    each window starts at the smallest pending reduced label lo (the first
+    window always, at s) and relaxes, round after round, the pending centers
+    below lo + width; a dropped label makes its center pending only below Db.
+    Returns the labels, from which the result follows as for pruned rounds."""
+    k = W.shape[0]
+
+    def in_weight(u):
+        if mode == 0:
+            return None if W[u, s] == pins.KEY_NONE else _delta(W[u, s])
+        return (int(pen[u]) if load[u] >= cap[u] else 0) - int(pen[s])
+
+    if mode == 0:
+        Db = 0
+    else:
+        others = [int(pot[u]) + in_weight(u) - int(pot[s]) for u in range(k) if u != s]
+        Db = -min(others) if others else -(1 << 46)
+    INF = (float("inf"), 0, 0)
+    lab = [INF] * k
+    lab[s] = (0, 0, -1)
+    pend = {s}
+    r = lambda v: lab[v][0] + int(pot[s]) - int(pot[v])
+    first = True
+    while pend:
+        lo = min(r(v) for v in pend)
+        if lo >= Db and not first:
+            break
+        first = False
+        while True:
+            front = sorted(v for v in pend if r(v) < lo + width)
+            if not front:
+                break
+            pend -= set(front)
+            new = list(lab)
+            for v in range(k):
+                if v == s:
+                    continue
+                for u in front:
+                    if W[u, v] == pins.KEY_NONE:
+                        continue
+                    c = (lab[u][0] + _delta(W[u, v]), lab[u][1] + 1, u)
+                    if c < new[v]:
+                        new[v] = c
+            for v in range(k):
+                if new[v] < lab[v] and new[v][0] + int(pot[s]) - int(pot[v]) < Db:
+                    pend.add(v)
+            lab = new
+    rel = [v for v in range(k) if lab[v] is not INF and (v == s or r(v) < Db)]
+    return {v: lab[v] for v in rel}
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("seed", range(100))
+def test_windowed_rounds_give_the_pruned_labels(seed, mode):
+    """Windowed rounds (any window width) give every center below the bound
+    the labels of the synchronous rounds, predecessor included, so the s_in
+    result and the potentials are those of pruned rounds."""
+    rng, k, pot, W, s, load, cap, pen = _case(seed, mode)
+    dist, pred, _ = oracle.refine_search(W, s, mode, load, cap, pen)
+    _, _, labels_p, _ = pruned_rounds(W, s, pot, mode, load, cap, pen)
+    for width in (1, 3, 10 ** 6):
+        labs = windowed_rounds(W, s, pot, mode, load, cap, pen, width)
+        assert set(labs) == set(labels_p), (seed, mode, width)
+        for v, (d, e, p) in labs.items():
+            if v != s:
+                assert d == dist[v] and p == pred[v], (seed, mode, width, v)

@@ -307,11 +307,34 @@ def test_search_ratio_extremes_bit_exact(lb, k):
             assert st["dijkstra"] > 0 and st["dijkstra_settled"] >= st["dijkstra"]
 
 
+@pytest.mark.parametrize("k", [12, 100, 200, 500])
+def test_sink_potentials_bit_exact(lb, k):
+    """Path searches on sink potentials (recomputed before every path search,
+    or every fifth), in Dijkstra order and by the measured choice, reach the
+    oracle's allotment."""
+    import torch
+    inst = L.random_small(k=k, n=3000, seed=700 + k, cm_hi=400, pen_hi=300)
+    say("sink potentials", inst.name)
+    ref = oracle.solve(*inst.arrays())
+    for every, ratio in ((1, 1 << 20), (5, 1 << 20), (5, lb.SEARCH_AUTO)):
+        with lb.Instance(torch.from_numpy(inst.cm).cuda(), inst.cap, inst.pen) as I:
+            I.set_option(lb.OPT_SINK_EVERY, every)
+            I.set_option(lb.OPT_SEARCH_RATIO, ratio)
+            assert I.get_option(lb.OPT_SINK_EVERY) == every
+            I.solve()
+            obj, a, st = I.objective(), I.assignment(), I.stats()
+        say("  every", every, "ratio", ratio, "sink", st["sink_potentials"], "settled", st["dijkstra_settled"])
+        assert obj == ref.objective and np.array_equal(a, ref.assign)
+        if st["path_searches"] > 0:
+            assert st["sink_potentials"] > 0
+
+
 def test_set_option_rejects_bad_values(lb):
     import torch
     inst = L.random_small(k=5, n=50, seed=3)
     with lb.Instance(torch.from_numpy(inst.cm).cuda(), inst.cap, inst.pen) as I:
-        for opt, val in ((lb.OPT_SEARCH_RATIO, -2), (lb.OPT_SEARCH_RATIO, (1 << 20) + 1), (99, 1)):
+        for opt, val in ((lb.OPT_SEARCH_RATIO, -2), (lb.OPT_SEARCH_RATIO, (1 << 20) + 1),
+                         (lb.OPT_SINK_EVERY, -1), (lb.OPT_SINK_EVERY, (1 << 20) + 1), (99, 1)):
             with pytest.raises(lb.LbddError) as e:
                 I.set_option(opt, val)
             assert e.value.code == lb.E_INVAL

@@ -137,3 +137,55 @@ def test_repair_from_failed_tails_restores_feasibility(seed):
     q = _repair(W2, p, tails)
     assert q is not None, seed
     assert feasible(W2, q), seed
+
+
+def _sink_model(W, q):
+    """The kernel's sink potentials: rounds from the sink over reversed edges,
+    sigma(v) = min(q(v), min_w W[v][w] + sigma(w)), every center in the first
+    frontier; None without convergence."""
+    k = W.shape[0]
+    sig = [int(x) for x in q]
+    front = list(range(k))
+    for _ in range(k + 1):
+        nxt = set()
+        for w in front:
+            for v in range(k):
+                if v == w or W[v, w] == pins.KEY_NONE:
+                    continue
+                c = sig[w] + pins.key_delta(W[v, w])
+                if c < sig[v]:
+                    sig[v] = c
+                    nxt.add(v)
+        if not nxt:
+            return sig
+        front = sorted(nxt)
+    return None
+
+
+@pytest.mark.parametrize("seed", range(80))
+def test_sink_potentials_are_distances_to_the_sink_and_feasible(seed):
+    """-sigma is a feasible potential, and sigma(v) is the cheapest cost of
+    placing one more unit starting from v (brute force over simple paths);
+    on such potentials the path search's bound term is smallest on the
+    center that ends a cheapest path."""
+    import itertools
+    rng = np.random.default_rng(3000 + seed)
+    k = int(rng.integers(2, 7))
+    W = _table(rng, k, int(rng.integers(0, k)))
+    if pins.has_negative_cycle(W):
+        return
+    q = rng.integers(0, 30, size=k)
+    sig = _sink_model(W, q)
+    assert sig is not None
+    assert feasible(W, [-x for x in sig])
+    for v in range(k):
+        best = int(q[v])
+        others = [u for u in range(k) if u != v]
+        for r in range(1, k):
+            for mid in itertools.permutations(others, r):
+                path = (v,) + mid
+                if any(W[a, b] == pins.KEY_NONE for a, b in zip(path, path[1:])):
+                    continue
+                cost = sum(pins.key_delta(W[a, b]) for a, b in zip(path, path[1:])) + int(q[path[-1]])
+                best = min(best, cost)
+        assert sig[v] == best, (seed, v)
