@@ -52,6 +52,36 @@ __device__ inline int lanes_below(uint64_t mask) {
                                         __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Minimum over the 64 lanes of a wavefront (all lanes active), in every
+// lane: within rows of 16 lanes by DPP (swap neighbours, swap pairs, mirror
+// the half-row, mirror the row), then across rows by swapping odd with even
+// rows and the upper with the lower half.  A swap hands each lane either its
+// own value or its partner's in one of its two results, so taking the minimum
+// of both is right whichever it is.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_min_step(uint32_t x) {
+  const uint32_t y = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, true);
+  return y < x ? y : x;
+}
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+  x = dpp_min_step<0xb1>(x);     // quad_perm [1,0,3,2]
+  x = dpp_min_step<0x4e>(x);     // quad_perm [2,3,0,1]
+  x = dpp_min_step<0x141>(x);    // row_half_mirror
+  x = dpp_min_step<0x140>(x);    // row_mirror
+  const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+  x = min(x, min((uint32_t)p[0], (uint32_t)p[1]));
+  const auto q = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  x = min(x, min((uint32_t)q[0], (uint32_t)q[1]));
+  return x;
+}
+// 64-bit minimum as two 32-bit ones: high words, then low words of the lanes
+// holding the smallest high word.  The result is the same in every lane.
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_min_u32((uint32_t)(x >> 32)));
+  const uint32_t lo = wave_min_u32((uint32_t)(x >> 32) == hi ? (uint32_t)x : 0xffffffffu);
+  return (uint64_t)hi << 32 | (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
+}
+
 struct Lds {
   uint64_t *W;      // [k][k] (LDS copy or the global table)
   uint32_t *wh;     // global high words of W while W is global, else null
@@ -102,7 +132,8 @@ struct Scalars {
   int32_t step_t;   // running mean of the device ticks per Dijkstra step, x16
   int32_t nsearch;  // searches run (Bellman-Ford or Dijkstra order)
   uint64_t bound;   // pruned Bellman-Ford: biased bound term (see bellman_ford)
-  uint64_t wlo;     // windowed rounds: smallest biased reduced label pending
+  uint64_t wlo[3];  // windowed rounds: smallest pending window key (see bellman_ford)
+  int32_t nrep[3];  // windowed rounds: repeated relaxations in a round
   int64_t wdelta;   // windowed rounds: window width (adapted per window)
   int32_t sink_every;  // path searches per sink-potential computation (0: never)
   int32_t sink_age;    // path searches since the last one
@@ -731,102 +762,172 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
   int64_t rounds = 0, relax = 0;
   bool conv = false;
   if (!WLDS && prune) {
-    // Windowed rounds (the table in global memory, potentials feasible):
-    // the centers whose label dropped since they were last relaxed are
-    // pending; each window takes the smallest pending reduced label lo and
-    // relaxes, round after round, only the pending centers below lo + width,
-    // until none is left there.  Reduced weights beyond the first hop are
-    // non-negative, so a center is mostly relaxed once, with its final
-    // label; the labels reach the same least fixpoint as in any order.  The
-    // search ends when no pending center is below the bound Db.
+    // Windowed rounds (the table in global memory, potentials feasible).
+    // The centers whose label dropped since they were last relaxed are
+    // pending.  A center's window key orders its label by reduced distance,
+    // then edges: key = ((r(v) + 2^46) << 11) | edges.  Each window starts at
+    // the smallest pending key lo and relaxes, round after round, the
+    // pending centers with keys below lo + width until none is left there.
+    // A pending center with the smallest key is final: a candidate through
+    // any other pending center u costs at least r(u) (reduced weights beyond
+    // the first hop are non-negative) with more edges than u, so its key is
+    // larger, predecessor ties included.  With width 1 every round relaxes
+    // only final labels, so each center is relaxed once; wider windows take
+    // fewer rounds but may relax a center again.  The width halves after a
+    // window that relaxed a center twice and doubles after a run of windows
+    // of one small round.  s goes first, alone (the edges out of s may be
+    // negative in reduced terms); the search ends when no pending center is
+    // below the bound Db.  Any order reaches the same least fixpoint of the
+    // labels.
+    // Each round is one pass over the pending flags (the frontier, and the
+    // smallest key of the pending centers left out) and one of relaxations
+    // (which adds the keys of the centers they make pending), so the next
+    // window's start is known when the round ends.
     int32_t *pend = L.mrow;                     // [k] 1: pending
-    for (int v = tid; v < k; v += NT) pend[v] = v == s;
-    __syncthreads();
-    const int64_t cap_rounds = 4 * (int64_t)k + 64;   // a safety net; never reached without a
-                                                      // negative cycle off s
-    conv = true;
-    for (bool first = true;; first = false) {
-      if (tid == 0) S.wlo = KEY_NONE;
-      __syncthreads();
-      for (int v = tid; v < k; v += NT)
-        if (pend[v]) {
-          const int64_t r = (int64_t)(lab[v] >> 22) - LAB_BIAS + pot_s - L.pot[v];
-          atomicMin((unsigned long long *)&S.wlo, (unsigned long long)(r + DIST_BIAS));
-        }
-      __syncthreads();
-      const uint64_t wl = S.wlo;
-      if (wl == KEY_NONE) break;
-      const int64_t lo = (int64_t)wl - DIST_BIAS;
-      if (lo >= Db && !first) break;             // the first window relaxes s itself
-      const int64_t hi = lo + S.wdelta;
-      int nf_first = -1;
-      for (;;) {
-        __syncthreads();                          // every thread read S.wlo / S.nfront
-        if (tid == 0) S.nfront[0] = 0;
-        __syncthreads();
-        // the pending centers of the window become the frontier, with
-        // their label bases and row offsets (see the rounds below)
-        for (int v = tid; v < k; v += NT)
-          if (pend[v]) {
-            const uint64_t l = lab[v];
-            const int64_t r = (int64_t)(l >> 22) - LAB_BIAS + pot_s - L.pot[v];
-            if (r < hi) {
-              pend[v] = 0;
-              const int j = atomicAdd(&S.nfront[0], 1);
-              L.front1[j] = v;
-              L.dist[j] = (int64_t)((l & ~(uint64_t)0x7ff) + (1ull << 11) + (uint32_t)v);
-              L.pred[j] = v * k;
-            }
-          }
-        __syncthreads();
-        const int nf = S.nfront[0];
-        if (nf == 0) break;
-        if (nf_first < 0) nf_first = nf;
-        const uint64_t *FB = reinterpret_cast<const uint64_t *>(L.dist);
-        constexpr int B = 4;
-        const int G = k <= NT ? NT / k : 1;
-        auto relax_pend = [&](int v, int j0) {
-          uint64_t best = KEY_NONE;
-          for (int j = j0; j < nf; j += B * G) {
-            uint64_t bs[B];
-            uint32_t hw[B];
-            bool ok[B];
-#pragma unroll
-            for (int x = 0; x < B; ++x) {
-              const int jj = j + x * G;
-              ok[x] = jj < nf;
-              const int idx = ok[x] ? jj : j;
-              bs[x] = FB[idx];
-              hw[x] = Whi[(uint32_t)(L.pred[idx] + v)];
-            }
-#pragma unroll
-            for (int x = 0; x < B; ++x) {
-              const uint64_t c = bs[x] + ((uint64_t)(int64_t)(int32_t)(hw[x] ^ 0x80000000u) << 22);
-              best = (ok[x] && hw[x] != 0xffffffffu && c < best) ? c : best;
-            }
-          }
-          if (best != KEY_NONE && best < atomicMin((unsigned long long *)&lab[v], (unsigned long long)best) &&
-              (int64_t)(best >> 22) - LAB_BIAS + pot_s - L.pot[v] < Db)
-            pend[v] = 1;
-        };
-        if (k <= NT) {
-          const int tv = tid % k, tg = tid / k;
-          if (tg < G && tv != s) relax_pend(tv, tg);
-        } else {
-          for (int v = tid; v < k; v += NT)
-            if (v != s) relax_pend(v, 0);
-        }
-        rounds += 1;
-        relax += (int64_t)nf * k;
-        if (rounds > cap_rounds) break;
-      }
-      if (rounds > cap_rounds) { conv = false; break; }
-      // aim at a few dozen centers per window
-      if (tid == 0) {
-        if (nf_first < 16) S.wdelta = S.wdelta < (1ll << 40) ? S.wdelta * 2 : S.wdelta;
-        else if (nf_first > 64) S.wdelta = S.wdelta > 1 ? S.wdelta / 2 : 1;
+    int32_t *seen = L.hop;                      // [k] window of the center's last relaxation
+    for (int v = tid; v < k; v += NT) {
+      pend[v] = v == s;
+      seen[v] = -1;
+    }
+    if (tid == 0) {
+      for (int c = 0; c < 3; ++c) {
+        S.nfront[c] = 0;
+        S.nrep[c] = 0;
+        S.wlo[c] = KEY_NONE;
       }
     }
+    __syncthreads();
+    auto wkey = [&](uint64_t l, int v) -> uint64_t {
+      const int64_t r = (int64_t)(l >> 22) - LAB_BIAS + pot_s - L.pot[v];
+      return (uint64_t)(r + DIST_BIAS) << 11 | ((l >> 11) & 0x7ff);
+    };
+    const uint64_t key_db = (uint64_t)(Db + DIST_BIAS) << 11;   // keys from here on: r >= Db
+    const int64_t cap_rounds = 2 * (int64_t)k + 64;   // a safety net: every round relaxes the
+                                                      // smallest pending key, which is final
+    int64_t width = S.wdelta;                   // uniform: every thread adapts its own copy
+    uint64_t hi = wkey(lab[s], s) + 1;          // window 0: s alone
+    int win = 0, win_rounds = 0, nf_first = 0, win_reps = 0, streak = 0;
+    conv = true;
+    for (int it = 0;; ++it) {
+      // counters c + 1 serve the next round: they were last read two rounds ago
+      const int c = it % 3;
+      if (tid == 0) {
+        S.nfront[(c + 1) % 3] = 0;
+        S.nrep[(c + 1) % 3] = 0;
+        S.wlo[(c + 1) % 3] = KEY_NONE;
+      }
+      // frontier: the pending centers below hi, with their label bases and
+      // row offsets (see the rounds below); one LDS atomic per wavefront for
+      // the slots, the repeats and the smallest key left out
+      for (int vb = 0; vb < k; vb += NT) {
+        const int v = vb + tid;
+        uint64_t l = 0, other = KEY_NONE;
+        bool take = false, rep = false;
+        if (v < k && pend[v]) {
+          l = lab[v];
+          const uint64_t key = wkey(l, v);
+          if (key < hi) {
+            take = true;
+            rep = seen[v] == win;
+            seen[v] = win;
+            pend[v] = 0;
+          } else {
+            other = key;
+          }
+        }
+        const uint64_t tmask = __ballot(take);
+        if (tmask) {
+          int base = 0;
+          if ((tid & 63) == 0) base = atomicAdd(&S.nfront[c], __popcll(tmask));
+          base = __builtin_amdgcn_readlane(base, 0);
+          if (take) {
+            const int j = base + lanes_below(tmask);
+            L.front1[j] = v;
+            L.dist[j] = (int64_t)((l & ~(uint64_t)0x7ff) + (1ull << 11) + (uint32_t)v);
+            L.pred[j] = v * k;
+          }
+        }
+        const uint64_t rmask = __ballot(rep);
+        if (rmask && (tid & 63) == 0) atomicAdd(&S.nrep[c], __popcll(rmask));
+        const uint64_t m = wave_min_u64(other);
+        if (m != KEY_NONE && (tid & 63) == 0) atomicMin((unsigned long long *)&S.wlo[c], (unsigned long long)m);
+      }
+      __syncthreads();
+      const int nf = S.nfront[c];
+      if (nf == 0) break;                       // hi is always above the smallest pending key
+      if (nf_first == 0) nf_first = nf;
+      win_rounds += 1;
+      win_reps += S.nrep[c];
+      const uint64_t *FB = reinterpret_cast<const uint64_t *>(L.dist);
+      constexpr int B = 4;
+      // candidate of target v over frontier entries j0, j0 + G, ...; returns
+      // the new key when v's label dropped below the bound (v is pending)
+      auto relax_pend = [&](int v, int j0) -> uint64_t {
+        uint64_t best = KEY_NONE;
+        for (int j = j0; j < nf; j += B * G) {
+          uint64_t bs[B];
+          uint32_t hw[B];
+          bool ok[B];
+#pragma unroll
+          for (int x = 0; x < B; ++x) {
+            const int jj = j + x * G;
+            ok[x] = jj < nf;
+            const int idx = ok[x] ? jj : j;
+            bs[x] = FB[idx];
+            hw[x] = Whi[(uint32_t)(L.pred[idx] + v)];
+          }
+#pragma unroll
+          for (int x = 0; x < B; ++x) {
+            const uint64_t cand = bs[x] + ((uint64_t)(int64_t)(int32_t)(hw[x] ^ 0x80000000u) << 22);
+            best = (ok[x] && hw[x] != 0xffffffffu && cand < best) ? cand : best;
+          }
+        }
+        if (best != KEY_NONE && best < atomicMin((unsigned long long *)&lab[v], (unsigned long long)best) &&
+            (int64_t)(best >> 22) - LAB_BIAS + pot_s - L.pot[v] < Db) {
+          pend[v] = 1;
+          return wkey(best, v);
+        }
+        return KEY_NONE;
+      };
+      for (int vb = 0; vb < (k <= NT ? 1 : k); vb += NT) {
+        uint64_t mk = KEY_NONE;
+        if (k <= NT) {
+          if (tg < G && tv != s) mk = relax_pend(tv, tg);
+        } else {
+          const int v = vb + tid;
+          if (v < k && v != s) mk = relax_pend(v, 0);
+        }
+        const uint64_t m = wave_min_u64(mk);
+        if (m != KEY_NONE && (tid & 63) == 0) atomicMin((unsigned long long *)&S.wlo[c], (unsigned long long)m);
+      }
+      rounds += 1;
+      relax += (int64_t)nf * k;
+      __syncthreads();                          // labels, pending flags and wlo[c] are in place
+      const uint64_t lo = S.wlo[c];             // the smallest pending key
+      if (lo >= hi || win == 0) {
+        // the window is done (s's after its one round: the centers it
+        // reaches may lie below s in reduced terms)
+        if (win > 0) {
+          if (win_reps > 0) {
+            width = width > 1 ? width / 2 : 1;
+            streak = 0;
+          } else if (win_rounds == 1 && nf_first < 8) {
+            if (++streak == 4) {
+              width = width < (1ll << 50) ? width * 2 : width;
+              streak = 0;
+            }
+          } else {
+            streak = 0;
+          }
+        }
+        if (lo == KEY_NONE || lo >= key_db) break;
+        hi = lo + (uint64_t)width;
+        win += 1;
+        win_rounds = nf_first = win_reps = 0;
+      }
+      if (rounds > cap_rounds) { conv = false; break; }
+    }
+    if (tid == 0) S.wdelta = width;
     __syncthreads();
   }
   for (int t = 1; t <= k + 1 && !(!WLDS && prune); ++t) {
@@ -1017,36 +1118,6 @@ __device__ __forceinline__ void sin_from_labels(const InstView &I, const Lds &L,
     }
   }
   __syncthreads();
-}
-
-// Minimum over the 64 lanes of a wavefront (all lanes active), in every
-// lane: within rows of 16 lanes by DPP (swap neighbours, swap pairs, mirror
-// the half-row, mirror the row), then across rows by swapping odd with even
-// rows and the upper with the lower half.  A swap hands each lane either its
-// own value or its partner's in one of its two results, so taking the minimum
-// of both is right whichever it is.
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_min_step(uint32_t x) {
-  const uint32_t y = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, true);
-  return y < x ? y : x;
-}
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
-  x = dpp_min_step<0xb1>(x);     // quad_perm [1,0,3,2]
-  x = dpp_min_step<0x4e>(x);     // quad_perm [2,3,0,1]
-  x = dpp_min_step<0x141>(x);    // row_half_mirror
-  x = dpp_min_step<0x140>(x);    // row_mirror
-  const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
-  x = min(x, min((uint32_t)p[0], (uint32_t)p[1]));
-  const auto q = __builtin_amdgcn_permlane32_swap(x, x, false, false);
-  x = min(x, min((uint32_t)q[0], (uint32_t)q[1]));
-  return x;
-}
-// 64-bit minimum as two 32-bit ones: high words, then low words of the lanes
-// holding the smallest high word.  The result is the same in every lane.
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_min_u32((uint32_t)(x >> 32)));
-  const uint32_t lo = wave_min_u32((uint32_t)(x >> 32) == hi ? (uint32_t)x : 0xffffffffu);
-  return (uint64_t)hi << 32 | (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
 }
 
 // Search from s in Dijkstra order by one wavefront, for when the node
@@ -1575,7 +1646,7 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
     S.sink_every = (int32_t)min(max(I.scalars[SC_SINK_EVERY], (int64_t)0), (int64_t)MAX_SINK_EVERY);
     S.sink_age = 0;
     S.potT_ok = 0;
-    S.wdelta = 64;
+    S.wdelta = 1ll << 11;   // one unit of reduced distance
     S.obj = I.scalars[SC_OBJECTIVE];
     S.status = (int32_t)I.scalars[SC_STATUS];
     for (int j = 0; j < SC_NSTATS; ++j) S.stats[j] = I.scalars[SC_STAT0 + j];

@@ -267,12 +267,15 @@ def test_pruned_rounds_match_synchronous_rounds(seed, mode):
     assert newpot[s] == 0
 
 
-def windowed_rounds(W, s, pot, mode, load, cap, pen, width):
-    """The kernel's windowed rounds: centers whose label dropped are pending;
-    each window starts at the smallest pending reduced label lo (the first
-    window always, at s) and relaxes, round after round, the pending centers
-    below lo + width; a dropped label makes its center pending only below Db.
-    Returns the labels, from which the result follows as for pruned rounds."""
+def windowed_rounds(W, s, pot, mode, load, cap, pen, width, counts=None):
+    """The kernel's windowed rounds: centers whose label dropped are pending,
+    ordered by their window key (reduced distance, then edges).  s goes
+    first, alone; then each window starts at the smallest pending key lo and
+    relaxes, round after round, the pending centers with keys below
+    lo + width (width in key units: one unit of reduced distance is 2^11).
+    A dropped label makes its center pending only below Db.  Returns the
+    labels, from which the result follows as for pruned rounds; counts, when
+    given, receives how often each center was relaxed."""
     k = W.shape[0]
 
     def in_weight(u):
@@ -290,27 +293,37 @@ def windowed_rounds(W, s, pot, mode, load, cap, pen, width):
     lab[s] = (0, 0, -1)
     pend = {s}
     r = lambda v: lab[v][0] + int(pot[s]) - int(pot[v])
-    first = True
+    key = lambda v: (r(v) << 11) | lab[v][1]
+
+    def relax(front):
+        new = list(lab)
+        for v in range(k):
+            if v == s:
+                continue
+            for u in front:
+                if W[u, v] == pins.KEY_NONE:
+                    continue
+                c = (lab[u][0] + _delta(W[u, v]), lab[u][1] + 1, u)
+                if c < new[v]:
+                    new[v] = c
+        for u in front:
+            if counts is not None:
+                counts[u] += 1
+        return new
+
+    pend.discard(s)
+    lab = relax([s])
+    pend |= {v for v in range(k) if lab[v] is not INF and v != s and r(v) < Db}
     while pend:
-        lo = min(r(v) for v in pend)
-        if lo >= Db and not first:
+        lo = min(key(v) for v in pend)
+        if lo >= Db << 11:
             break
-        first = False
         while True:
-            front = sorted(v for v in pend if r(v) < lo + width)
+            front = sorted(v for v in pend if key(v) < lo + width)
             if not front:
                 break
             pend -= set(front)
-            new = list(lab)
-            for v in range(k):
-                if v == s:
-                    continue
-                for u in front:
-                    if W[u, v] == pins.KEY_NONE:
-                        continue
-                    c = (lab[u][0] + _delta(W[u, v]), lab[u][1] + 1, u)
-                    if c < new[v]:
-                        new[v] = c
+            new = relax(front)
             for v in range(k):
                 if new[v] < lab[v] and new[v][0] + int(pot[s]) - int(pot[v]) < Db:
                     pend.add(v)
@@ -328,9 +341,33 @@ def test_windowed_rounds_give_the_pruned_labels(seed, mode):
     rng, k, pot, W, s, load, cap, pen = _case(seed, mode)
     dist, pred, _ = oracle.refine_search(W, s, mode, load, cap, pen)
     _, _, labels_p, _ = pruned_rounds(W, s, pot, mode, load, cap, pen)
-    for width in (1, 3, 10 ** 6):
+    for width in (1, 3, 2 ** 11, 3 * 2 ** 11 + 5, 10 ** 12):
         labs = windowed_rounds(W, s, pot, mode, load, cap, pen, width)
         assert set(labs) == set(labels_p), (seed, mode, width)
         for v, (d, e, p) in labs.items():
             if v != s:
                 assert d == dist[v] and p == pred[v], (seed, mode, width, v)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("seed", range(60))
+def test_width_one_windows_relax_each_center_once(seed, mode):
+    """With width 1 a window holds one key, and the pending center with the
+    smallest key is final, so no center is relaxed twice."""
+    rng, k, pot, W, s, load, cap, pen = _case(seed, mode)
+    counts = [0] * k
+    windowed_rounds(W, s, pot, mode, load, cap, pen, 1, counts)
+    assert max(counts) <= 1, (seed, mode, counts)
+
+
+def test_one_wide_window_relaxes_centers_again():
+    """The contrast: one window over every key relaxes a center whose label
+    drops again (most of these inputs have one)."""
+    again = 0
+    for mode in (0, 1):
+        for seed in range(60):
+            rng, k, pot, W, s, load, cap, pen = _case(seed, mode)
+            counts = [0] * k
+            windowed_rounds(W, s, pot, mode, load, cap, pen, 10 ** 12, counts)
+            again += max(counts) > 1
+    assert again > 30
