@@ -103,7 +103,8 @@ struct Lds {
   int32_t *mfrom;   // [k+1]
   int32_t *mto;     // [k+1]
   int32_t *trow;    // [k+1] columns to refill
-  uint64_t *wmin;   // [2][NT/64] per-wavefront minima of a refill round
+  uint64_t *wmin;   // [NT/64][BEST_M] per-wavefront candidates of a refill (also
+                    // per-wavefront minima of other reductions)
 };
 
 // W[u][w] = key (idx = u k + w), its high word when W is global, and the
@@ -149,7 +150,7 @@ __host__ __device__ size_t solve_lds_bytes(int k, bool wlds) {
   const size_t K1 = (size_t)k + 1;
   size_t b = K1 * 8 * 2 + K1 * 4 * 4 + 8 + (size_t)k * 8 * 3 + ((size_t)k + 31) / 32 * 4 + 8 +
              (size_t)k * 4 * 3 +
-             K1 * 4 * 3 + K1 * 4 + 8 + 2 * (SOLVE_THREADS / 64) * 8;
+             K1 * 4 * 3 + K1 * 4 + 8 + (SOLVE_THREADS / 64) * BEST_M * 8;
   if (wlds) b += (size_t)k * k * 8;
   return b;
 }
@@ -305,18 +306,18 @@ __device__ __forceinline__ void move_lists(const InstView &I, const Lds &L, int 
   __syncthreads();
 }
 
-__device__ inline uint64_t shfl_xor_u64(uint64_t v, int mask) {
-  const uint32_t lo = __shfl_xor((uint32_t)v, mask, 64);
-  const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), mask, 64);
-  return (uint64_t)hi << 32 | lo;
-}
-
 // Refill the list of (u, w) from the members of u: the BEST_M smallest keys
-// (definition of Gamma), by per-thread top lists merged in BEST_M rounds of a
-// workgroup min (wavefront shuffles + one LDS exchange per round).
+// (definition of Gamma).  Every thread keeps a sorted top list of its member
+// rows; each wavefront takes its BEST_M smallest by BEST_M wavefront minima
+// (the one lane holding a minimum pops it: keys are unique), and wavefront 0
+// takes the BEST_M smallest of those NT / 64 * BEST_M candidates the same
+// way, two per lane.  Two barriers in all.  The wavefront minima use DPP and
+// lane swaps that read every lane: they run with all 64 lanes active (a
+// disabled lane would read as 0, the smallest key).
 __device__ __forceinline__ void refill_column(const InstView &I, const Lds &L, Scalars &S, int u, int w) {
   const int k = I.k;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int m = L.load[u];
   const int32_t *mem = I.members + (int64_t)u * I.n;
   uint64_t b[BEST_M];
@@ -335,36 +336,47 @@ __device__ __forceinline__ void refill_column(const InstView &I, const Lds &L, S
     const int32_t *ry = I.cm + (int64_t)y * k;
     list_merge(b, pack_key(ry[w] - ry[u], (uint32_t)y));
   }
-  const int wave = tid >> 6;
-  uint64_t out[BEST_M];
+  // this wavefront's BEST_M smallest: lane r keeps the r-th
+  uint64_t mine = KEY_NONE;
 #pragma unroll
   for (int r = 0; r < BEST_M; ++r) {
-    uint64_t g = b[0];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) g = umin(g, shfl_xor_u64(g, off));
-    if ((tid & 63) == 0) L.wmin[(r & 1) * (NT / 64) + wave] = g;
-    __syncthreads();
-    uint64_t gm = KEY_NONE;
-#pragma unroll
-    for (int j = 0; j < NT / 64; ++j) gm = umin(gm, L.wmin[(r & 1) * (NT / 64) + j]);
-    out[r] = gm;
-    if (gm != KEY_NONE && b[0] == gm) {          // keys are unique: one owner pops
+    const uint64_t g = wave_min_u64(b[0]);
+    mine = lane == r ? g : mine;
+    if (g != KEY_NONE && b[0] == g) {
 #pragma unroll
       for (int j = 0; j < BEST_M - 1; ++j) b[j] = b[j + 1];
       b[BEST_M - 1] = KEY_NONE;
     }
   }
-  if (tid == 0) {
-    const int64_t idx = (int64_t)u * k + w;
-    list_store(I.best + idx * BEST_M, out);
-    int c = 0;
+  if (lane < BEST_M) L.wmin[wave * BEST_M + lane] = mine;
+  __syncthreads();
+  if (wave == 0) {
+    // NT / 64 * BEST_M = 128 candidates, two per lane (sorted pair)
+    static_assert(NT / 64 * BEST_M == 128, "two candidates per lane of one wavefront");
+    const uint64_t x0 = L.wmin[lane], x1 = L.wmin[lane + 64];
+    uint64_t c0 = umin(x0, x1), c1 = x0 < x1 ? x1 : x0;
+    uint64_t out[BEST_M];
 #pragma unroll
-    for (int j = 0; j < BEST_M; ++j) c += out[j] != KEY_NONE;
-    I.meta[idx] = (uint8_t)(c | (m <= BEST_M ? META_ALL : 0));
-    I.thr[idx] = list_threshold(out, c, m <= BEST_M);
-    set_w(L, k, u, w, idx, out[0]);
-    S.stats[ST_ROWS_SCANNED] += m;
-    S.stats[ST_REFILLS] += 1;
+    for (int r = 0; r < BEST_M; ++r) {
+      const uint64_t g = wave_min_u64(c0);
+      out[r] = g;
+      if (g != KEY_NONE && c0 == g) {
+        c0 = c1;
+        c1 = KEY_NONE;
+      }
+    }
+    if (tid == 0) {
+      const int64_t idx = (int64_t)u * k + w;
+      list_store(I.best + idx * BEST_M, out);
+      int c = 0;
+#pragma unroll
+      for (int j = 0; j < BEST_M; ++j) c += out[j] != KEY_NONE;
+      I.meta[idx] = (uint8_t)(c | (m <= BEST_M ? META_ALL : 0));
+      I.thr[idx] = list_threshold(out, c, m <= BEST_M);
+      set_w(L, k, u, w, idx, out[0]);
+      S.stats[ST_ROWS_SCANNED] += m;
+      S.stats[ST_REFILLS] += 1;
+    }
   }
   __syncthreads();
 }
@@ -874,7 +886,7 @@ __device__ __forceinline__ bool bellman_ford(const InstView &I, const Lds &L, Sc
             ok[x] = jj < nf;
             const int idx = ok[x] ? jj : j;
             bs[x] = FB[idx];
-            hw[x] = Whi[(uint32_t)(L.pred[idx] + v)];
+            hw[x] = Whi[WS * (uint32_t)(L.pred[idx] + v)];
           }
 #pragma unroll
           for (int x = 0; x < B; ++x) {
