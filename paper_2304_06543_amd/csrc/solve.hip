@@ -85,7 +85,7 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
 struct Lds {
   uint64_t *W;      // [k][k] (LDS copy or the global table)
   uint32_t *wh;     // global high words of W while W is global, else null
-  uint32_t *wt;     // global high words of W transposed (kept in every launch)
+  uint32_t *wt;     // global high words of W transposed (kept while W is global)
   uint64_t *red;    // [k+1] per-target minimum
   int64_t *dist;    // [k+1]
   int32_t *pred;    // [k+1]
@@ -107,12 +107,15 @@ struct Lds {
                     // per-wavefront minima of other reductions)
 };
 
-// W[u][w] = key (idx = u k + w), its high word when W is global, and the
-// transposed high word
+// W[u][w] = key (idx = u k + w) and, when W is global, its high word in the
+// packed and in the transposed array (with W in LDS the searches read both
+// from the LDS copy)
 __device__ inline void set_w(const Lds &L, int k, int u, int w, int64_t idx, uint64_t key) {
   L.W[idx] = key;
-  if (L.wh) L.wh[idx] = (uint32_t)(key >> 32);
-  L.wt[(int64_t)w * k + u] = (uint32_t)(key >> 32);
+  if (L.wh) {
+    L.wh[idx] = (uint32_t)(key >> 32);
+    L.wt[(int64_t)w * k + u] = (uint32_t)(key >> 32);
+  }
 }
 
 struct Scalars {
@@ -662,7 +665,8 @@ __device__ __forceinline__ void sink_potential(const InstView &I, const Lds &L, 
       const int j = (int)(x / k), v = (int)(x - (int64_t)j * k);
       const int w = F[j];
       if (v == w) continue;
-      const uint32_t hi = L.wt[(int64_t)w * k + v];   // W[v][w]
+      const uint32_t hi = WLDS ? (uint32_t)(L.W[(int64_t)v * k + w] >> 32)
+                               : L.wt[(int64_t)w * k + v];   // W[v][w]
       if (hi == 0xffffffffu) continue;
       const uint64_t c = lab[w] + (uint64_t)(int64_t)(int32_t)(hi ^ 0x80000000u);
       if (c < atomicMin((unsigned long long *)&lab[v], (unsigned long long)c) &&
@@ -1641,7 +1645,12 @@ __device__ __forceinline__ void solve_range(const InstView &I, int64_t r_begin, 
   if (WLDS)
     for (int64_t i = tid; i < (int64_t)k * k; i += NT) L.W[i] = I.W[i];
   else   // a launch that kept W in LDS left the high words behind
-    for (int64_t i = tid; i < (int64_t)k * k; i += NT) L.wh[i] = (uint32_t)(I.W[i] >> 32);
+    for (int64_t i = tid; i < (int64_t)k * k; i += NT) {
+      const uint32_t hi = (uint32_t)(I.W[i] >> 32);
+      const int u = (int)(i / k), w = (int)(i - (int64_t)u * k);
+      L.wh[i] = hi;
+      L.wt[(int64_t)w * k + u] = hi;
+    }
   for (int i = tid; i < k; i += NT) L.pot[i] = 0;
   for (int i = tid; i < (k + 31) / 32; i += NT) L.dirty[i] = 0;
   for (int i = tid; i < k; i += NT) { L.load[i] = I.load[i]; L.cap[i] = I.cap[i]; L.pen[i] = I.pen[i]; }
