@@ -16,10 +16,11 @@ Prints one JSON line.  Besides the contract's fields:
                 bytes per second against HBM peak, timed with HIP events on
                 the stream it runs on; it is bound by dependent latency in one
                 workgroup, not by bandwidth (bound "latency")
-  c3            k=500, n=1,000,000 (2 GB of costs): its first 300,000
-                iterations (--c3 whole: the whole solve), timed with HIP
-                events, allotment, loads, objective and table against the
-                stored oracle result, and a bounded oracle sample beside it
+  c3            k=500, n=1,000,000 (2 GB of costs): one whole solve (--c3
+                prefix: its first 300,000 iterations), timed with HIP events,
+                allotment, loads and objective (and, for the prefix, the
+                table) against the stored oracle result, and a bounded oracle
+                sample beside it
   scan          the whole-matrix best-transfer scan at k=500, n=1,000,000
                 with its own roofline (HBM-bound), next to a hand-written
                 read-only streaming kernel and a torch copy as ceilings
@@ -585,7 +586,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip every oracle timing")
-    ap.add_argument("--c3", choices=("whole", "prefix", "skip"), default="prefix",
+    ap.add_argument("--c3", choices=("whole", "prefix", "skip"), default="whole",
                     help="k=500, n=1,000,000: one whole solve, or its first 300,000 iterations")
     ap.add_argument("--c3-cpu-iters", type=int, default=2000,
                     help="iterations of the k=500 instance in the bounded oracle sample")
