@@ -52,8 +52,10 @@ enum {
     LBDD_E_NOMEM = -2,    /* device or host allocation failed */
     LBDD_E_DEVICE = -3,   /* a HIP runtime call failed */
     LBDD_E_STATE = -4,    /* call not valid in the handle's current state */
-    LBDD_E_INTERNAL = -5  /* an invariant failed (e.g. Bellman-Ford found a
+    LBDD_E_INTERNAL = -5, /* an invariant failed (e.g. Bellman-Ford found a
                              negative cycle that Lemmas 1-2 rule out) */
+    LBDD_E_CANCELLED = -6,/* a server job was cancelled before it started */
+    LBDD_E_TIMEOUT = -7   /* a server job waited longer than the queue timeout */
 };
 
 #define LBDD_MAX_K 2048                /* centers per instance */
@@ -307,9 +309,23 @@ int lbdd_server_wait(lbdd_server *srv, uint64_t ticket, int64_t *objective);
  * (not finished), or the job's own error. */
 int lbdd_server_result(lbdd_server *srv, uint64_t ticket, int32_t *assign, double *times);
 
+/* Cancel a job that is still waiting for admission: it leaves the queue,
+ * its state becomes LBDD_E_CANCELLED and its cost matrix is no longer
+ * borrowed (lbdd_server_result then releases the ticket).  A job already on
+ * the device runs to completion.  Errors: LBDD_E_INVAL (unknown ticket),
+ * LBDD_E_STATE (the job is running or finished). */
+int lbdd_server_cancel(lbdd_server *srv, uint64_t ticket);
+
+/* Queue timeout in seconds (0: none, the default): a job that has waited
+ * longer than this for admission leaves the queue with state
+ * LBDD_E_TIMEOUT.  Jobs already admitted are not affected.  Errors:
+ * LBDD_E_INVAL (negative or not finite). */
+int lbdd_server_set_queue_timeout(lbdd_server *srv, double seconds);
+
 /* Counters (int64): [0] submitted [1] admitted [2] finished [3] failed
  * [4] service kernel launches [5] peak jobs in flight [6] peak bytes admitted
- * [7] bytes admitted now [8] workers.  Returns the number written. */
+ * [7] bytes admitted now [8] workers [9] cancelled [10] timed out.  Returns
+ * the number written. */
 int lbdd_server_stats(lbdd_server *srv, int64_t *out, int32_t count);
 
 /* Stop: waiting jobs are dropped (their state becomes LBDD_E_STATE), jobs

@@ -38,6 +38,24 @@ struct AdmissionQueue {
     return false;
   }
 
+  // Remove every waiting request whose id satisfies pred (expiry), passing
+  // each removed id to out; returns how many were removed.
+  template <class Pred, class Out>
+  size_t erase_if(Pred pred, Out out) {
+    size_t m = 0;
+    for (auto it = q_.begin(); it != q_.end();) {
+      if (pred(it->id)) {
+        if (it == q_.begin()) bypassed_ = 0;
+        out(it->id);
+        it = q_.erase(it);
+        ++m;
+      } else {
+        ++it;
+      }
+    }
+    return m;
+  }
+
   // Next request to admit given the free budget, the number of jobs in flight
   // and whether a job slot is free; sets *id and returns true, or false when
   // nothing may be admitted now.  The chosen request is removed.

@@ -83,7 +83,9 @@ struct lbdd_server {
   uint64_t next_id = 1;
   int64_t published = 0;
   size_t in_use = 0;
-  int64_t stats[8] = {0};            // submitted, admitted, finished, failed, launches, peak jobs, peak bytes
+  int64_t stats[10] = {0};           // submitted, admitted, finished, failed, launches, peak jobs,
+                                     // peak bytes, (unused), cancelled, timed out
+  double queue_timeout = 0;          // seconds a job may wait for admission (0: no limit)
 
   int ensure_kernel() {
     if (kernel_launched && hipEventQuery(kernel_end) == hipErrorNotReady) return LBDD_OK;
@@ -101,6 +103,17 @@ struct lbdd_server {
 void lbdd_server::loop() {
   std::unique_lock<std::mutex> lk(mu);
   while (true) {
+    // 0. jobs that waited longer than the queue timeout leave the queue
+    if (queue_timeout > 0 && !queue.empty()) {
+      const double now = wall() - t0;
+      const size_t m = queue.erase_if(
+          [&](uint64_t id) { return now - jobs[id].t_submit > queue_timeout; },
+          [&](uint64_t id) { jobs[id].state = LBDD_E_TIMEOUT; jobs[id].cm = nullptr; });
+      if (m) {
+        stats[9] += (int64_t)m;
+        cv.notify_all();
+      }
+    }
     // 1. admission
     for (;;) {
       const int64_t seq = published;
@@ -295,12 +308,35 @@ int lbdd_server_result(lbdd_server *s, uint64_t ticket, int32_t *assign, double 
   return st == LBDD_JOB_DONE ? LBDD_OK : lbdd::fail(st, "job failed");
 }
 
+int lbdd_server_cancel(lbdd_server *s, uint64_t ticket) {
+  if (!s) return lbdd::fail(LBDD_E_INVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->jobs.find(ticket);
+  if (it == s->jobs.end()) return lbdd::fail(LBDD_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  if (it->second.state != LBDD_JOB_QUEUED || !s->queue.erase(ticket))
+    return lbdd::fail(LBDD_E_STATE, "job %llu is not waiting", (unsigned long long)ticket);
+  it->second.state = LBDD_E_CANCELLED;
+  it->second.cm = nullptr;
+  s->stats[8] += 1;
+  s->cv.notify_all();
+  return LBDD_OK;
+}
+
+int lbdd_server_set_queue_timeout(lbdd_server *s, double seconds) {
+  if (!s) return lbdd::fail(LBDD_E_INVAL, "NULL argument");
+  if (!(seconds >= 0) || seconds > 1e9) return lbdd::fail(LBDD_E_INVAL, "timeout must be finite and >= 0");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->queue_timeout = seconds;
+  s->cv.notify_all();
+  return LBDD_OK;
+}
+
 int lbdd_server_stats(lbdd_server *s, int64_t *out, int32_t count) {
   if (!s || count < 0 || (count > 0 && !out)) return lbdd::fail(LBDD_E_INVAL, "bad argument");
   std::lock_guard<std::mutex> lk(s->mu);
-  int64_t all[9] = {s->stats[0], s->stats[1], s->stats[2], s->stats[3], s->stats[4], s->stats[5],
-                    s->stats[6], (int64_t)s->in_use, (int64_t)s->workers};
-  const int m = count < 9 ? count : 9;
+  int64_t all[11] = {s->stats[0], s->stats[1], s->stats[2], s->stats[3], s->stats[4], s->stats[5],
+                     s->stats[6], (int64_t)s->in_use, (int64_t)s->workers, s->stats[8], s->stats[9]};
+  const int m = count < 11 ? count : 11;
   for (int i = 0; i < m; ++i) out[i] = all[i];
   return m;
 }

@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbdd.so")
 
-OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_INTERNAL = 0, -1, -2, -3, -4, -5
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_INTERNAL, E_CANCELLED, E_TIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
 CM_DEVICE = 0x1
 OUT_DEVICE = 0x1
 MAX_K = 2048
@@ -45,10 +45,11 @@ EXPORTS = ("lbdd_create", "lbdd_solve", "lbdd_solve_iters", "lbdd_solve_batch", 
            "lbdd_tune_best_transfers", "lbdd_create_strict", "lbdd_centers",
            "lbdd_create_penalty_table", "lbdd_road_cm_work_bytes", "lbdd_road_cost_matrix",
            "lbdd_best_transfers_batch_work_bytes", "lbdd_best_transfers_batch",
-           "lbdd_best_transfers_noalloc", "lbdd_read_ceiling")
+           "lbdd_best_transfers_noalloc", "lbdd_read_ceiling", "lbdd_server_cancel",
+           "lbdd_server_set_queue_timeout")
 JOB_QUEUED, JOB_RUNNING, JOB_DONE = 0, 1, 2
 SERVER_STATS = ("submitted", "admitted", "finished", "failed", "kernel_launches",
-                "peak_jobs", "peak_bytes", "bytes_now", "workers")
+                "peak_jobs", "peak_bytes", "bytes_now", "workers", "cancelled", "timed_out")
 
 _lib = None
 
@@ -89,6 +90,8 @@ def load(path: str = LIB_PATH):
         "lbdd_server_result": ([P, C.c_uint64, P, P], C.c_int),
         "lbdd_server_stats": ([P, P, I32], C.c_int),
         "lbdd_server_destroy": ([P], None),
+        "lbdd_server_cancel": ([P, C.c_uint64], C.c_int),
+        "lbdd_server_set_queue_timeout": ([P, C.c_double], C.c_int),
         "lbdd_set_option": ([P, I32, I64], C.c_int),
         "lbdd_get_option": ([P, I32, C.POINTER(I64)], C.c_int),
         "lbdd_tune_search": ([I32, I64, P, P, P, U32, I64, P, C.POINTER(I64), P, I32], C.c_int),
@@ -503,6 +506,16 @@ class Server:
         finally:
             self._keep.pop(ticket, None)
         return a, tuple(times)
+
+    def cancel(self, ticket: int):
+        """Take a job that is still waiting out of the queue (its state
+        becomes E_CANCELLED); a running or finished job raises (E_STATE)."""
+        _check(self._lib.lbdd_server_cancel(self._s, int(ticket)))
+
+    def set_queue_timeout(self, seconds: float):
+        """Jobs that wait longer than this for admission fail with E_TIMEOUT
+        (0: no limit)."""
+        _check(self._lib.lbdd_server_set_queue_timeout(self._s, float(seconds)))
 
     def stats(self) -> dict:
         out = np.zeros(len(SERVER_STATS), np.int64)

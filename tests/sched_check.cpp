@@ -49,6 +49,20 @@ int main() {
     CHECK(!q.erase(7));
     CHECK(q.next(10, 0, true, &id) && id == 2);
   }
+  {  // expiry: every matching request leaves, the others keep their order
+    AdmissionQueue q(1);
+    for (uint64_t i = 1; i <= 6; ++i) q.push(i, i == 1 ? 1000 : 10);
+    CHECK(q.next(100, 1, true, &id) && id == 2);      // one bypass of request 1
+    CHECK(!q.next(100, 1, true, &id));                // cap reached
+    std::vector<uint64_t> gone;
+    CHECK(q.erase_if([](uint64_t x) { return x == 1 || x == 4; }, [&](uint64_t x) { gone.push_back(x); }) == 2);
+    CHECK(gone.size() == 2 && gone[0] == 1 && gone[1] == 4);
+    CHECK(q.next(100, 1, true, &id) && id == 3);      // the head left: the counter restarted
+    CHECK(q.next(100, 1, true, &id) && id == 5);
+    CHECK(q.next(100, 1, true, &id) && id == 6);
+    CHECK(q.empty());
+    CHECK(q.erase_if([](uint64_t) { return true; }, [](uint64_t) {}) == 0);
+  }
   {  // footprint grows with both sizes and covers the cost matrix three times
     CHECK(lbdd::instance_footprint(100, 100000) > (size_t)3 * 4 * 100 * 100000);
     CHECK(lbdd::instance_footprint(200, 1000) > lbdd::instance_footprint(100, 1000));

@@ -122,3 +122,80 @@ def test_destroy_with_waiting_jobs(lb):
     for i in insts:
         srv.submit(*i.arrays())
     srv.close()                                           # must not hang
+
+
+def _long_job():
+    """C2: about 0.7 s of solve, long enough for the queue tests below."""
+    return L.make_config("C2")
+
+
+def test_cancel_a_waiting_job(lb):
+    """With one job slot, a second job waits; cancelling it takes it out of
+    the queue, the running job finishes unchanged, and a job that is running,
+    finished or unknown cannot be cancelled."""
+    big = _long_job()
+    small = L.random_small(k=8, n=500, seed=77, cm_hi=500, cap="tight", pen_hi=400)
+    ref_small = oracle.solve(*small.arrays())
+    with lb.Server(hbm_budget=8 << 30, max_jobs=1) as srv:
+        t1 = srv.submit(*big.arrays())
+        t2 = srv.submit(*small.arrays())
+        t3 = srv.submit(*small.arrays())
+        srv.cancel(t2)
+        assert srv.poll(t2)[0] == lb.E_CANCELLED
+        with pytest.raises(lb.LbddError) as e:
+            srv.cancel(t2)                                  # no longer waiting
+        assert e.value.code == lb.E_STATE
+        with pytest.raises(lb.LbddError) as e:
+            srv.cancel(123456)
+        assert e.value.code == lb.E_INVAL
+        with pytest.raises(lb.LbddError) as e:
+            srv.wait(t2)
+        assert e.value.code == lb.E_CANCELLED
+        with pytest.raises(lb.LbddError) as e:
+            srv.result(t2)                                  # releases the ticket
+        assert e.value.code == lb.E_CANCELLED
+        while srv.poll(t1)[0] == lb.JOB_QUEUED:
+            time.sleep(0.001)
+        if srv.poll(t1)[0] == lb.JOB_RUNNING:
+            with pytest.raises(lb.LbddError) as e:
+                srv.cancel(t1)
+            assert e.value.code == lb.E_STATE
+        obj1 = srv.wait(t1)
+        assert srv.wait(t3) == ref_small.objective
+        a3, _ = srv.result(t3)
+        assert np.array_equal(a3, ref_small.assign)
+        srv.result(t1)
+        st = srv.stats()
+        assert st["cancelled"] == 1 and st["finished"] == 2 and st["timed_out"] == 0
+        say("cancel: long job objective", obj1, "stats", st)
+
+
+def test_queue_timeout(lb):
+    """A job that waits longer than the queue timeout fails with E_TIMEOUT;
+    the running job and jobs submitted after the timeout is lifted are
+    unaffected."""
+    big = _long_job()
+    small = L.random_small(k=20, n=800, seed=78, cm_hi=500, cap="tight", pen_hi=400)
+    ref_small = oracle.solve(*small.arrays())
+    with lb.Server(hbm_budget=8 << 30, max_jobs=1) as srv:
+        with pytest.raises(lb.LbddError) as e:
+            srv.set_queue_timeout(-1.0)
+        assert e.value.code == lb.E_INVAL
+        srv.set_queue_timeout(0.05)
+        t1 = srv.submit(*big.arrays())
+        t2 = srv.submit(*small.arrays())
+        with pytest.raises(lb.LbddError) as e:
+            srv.wait(t2)
+        assert e.value.code == lb.E_TIMEOUT
+        assert srv.poll(t2)[0] == lb.E_TIMEOUT
+        with pytest.raises(lb.LbddError):
+            srv.result(t2)
+        srv.set_queue_timeout(0)
+        t3 = srv.submit(*small.arrays())
+        srv.wait(t1)
+        srv.result(t1)
+        assert srv.wait(t3) == ref_small.objective
+        a3, _ = srv.result(t3)
+        assert np.array_equal(a3, ref_small.assign)
+        st = srv.stats()
+        assert st["timed_out"] == 1 and st["finished"] == 2
