@@ -418,14 +418,20 @@ int lbdd_best_transfers_batch(int32_t m, const int32_t *k, const int64_t *n, con
 /* ---- autotuner -------------------------------------------------------------
  * Both calls time choices that leave every result unchanged and record the
  * fastest in a lock-guarded table of this process.  An instance takes its
- * search ratio from the table when it is created; a scan looks its tile
- * configuration up when it is launched.
+ * search ratio from the table when it is created (looked up by its k bucket,
+ * the bit length of k, and its n bucket, the number of decimal digits of n
+ * minus one); a scan looks its tile configuration up (by k and load width)
+ * when it is launched.  The tables can be saved to and loaded from a JSON
+ * tuning cache (lbdd_tune_save / lbdd_tune_load); when the environment
+ * variable LBDD_TUNE_CACHE names one, the library loads it for the current
+ * device's architecture on its first lookup, so instances, batches and the
+ * server start tuned.
  *
  * lbdd_tune_search: creates a fresh instance from the inputs (arguments as
  * lbdd_create) once per candidate search ratio (-1, 0, 64, 2^20), times its
  * first `iters` iterations with HIP events on `hip_stream`, checks that all
  * candidates reach the same objective, and records the fastest ratio for
- * this k (used by later lbdd_create calls) if it beats the default (-1) by
+ * this k and n bucket (used by later lbdd_create calls) if it beats the default (-1) by
  * more than 2 %, else the default.  A short prefix has few searches: time
  * enough iterations (up to n) to tell the candidates apart.  Writes it to
  * *ratio_out and the candidates' times in ms to ms_out[0 .. count-1].
@@ -453,6 +459,27 @@ int lbdd_tune_search(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap
 int lbdd_tune_best_transfers(int32_t k, int64_t n, const int32_t *cm, const int32_t *assign,
                              const int32_t *rank, uint64_t *W, void *work, int32_t reps,
                              void *hip_stream, int32_t *config_out, float *ms_out);
+
+/* The tuning cache: a JSON file {"format": "lbdd-tune-1", "entries": [...]}
+ * whose entries carry the architecture they were tuned on ("arch", e.g.
+ * "gfx950") and either a search ratio for a (k bucket, n bucket) or a scan
+ * configuration for a (k, load width).
+ * lbdd_tune_save writes every entry of this process's tables, tagged with
+ * `arch` (NULL: the current device's), replacing the file (written to
+ * path.tmp, then renamed).  Returns the number of entries written, or
+ * LBDD_E_INVAL (NULL path, unwritable file), LBDD_E_DEVICE (no device to
+ * name the architecture).
+ * lbdd_tune_load reads such a file and applies the entries tuned on `arch`
+ * (NULL: the current device's); entries of other architectures are skipped.
+ * Every entry is checked first (ratio range, a scan shape this library has
+ * that covers k), and a file with any bad entry changes nothing.  Returns
+ * the number of entries applied, or LBDD_E_INVAL (unreadable, not JSON,
+ * another format, a bad entry), LBDD_E_DEVICE.
+ * lbdd_tune_clear empties both tables (every lookup then gives the
+ * defaults).  None of the three launches device work. */
+int lbdd_tune_save(const char *path, const char *arch);
+int lbdd_tune_load(const char *path, const char *arch);
+void lbdd_tune_clear(void);
 
 #ifdef __cplusplus
 }

@@ -230,7 +230,7 @@ int create_instance(int32_t k, int64_t n, const int32_t *cm, const int32_t *capa
     if ((e = lbdd::launch_init_state(h->view(), h->st)) != hipSuccess) { rc = hip_fail(e, "init kernel"); break; }
     // the per-instance options, in adjacent scalar slots
     static_assert(lbdd::SC_SINK_EVERY == lbdd::SC_RATIO + 1, "option slots");
-    opts[0] = lbdd::tuned_search_ratio(k);
+    opts[0] = lbdd::tuned_search_ratio(k, n);
     opts[1] = lbdd::DEFAULT_SINK_EVERY;
     if ((e = hipMemcpyAsync(h->scalars + lbdd::SC_RATIO, opts, sizeof opts, hipMemcpyHostToDevice, h->st)) != hipSuccess) {
       rc = hip_fail(e, "init options"); break;

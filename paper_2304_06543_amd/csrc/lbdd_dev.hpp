@@ -2,6 +2,8 @@
 // the MI355X ASRAL solver.  gfx950 only: wave64, 160 KB LDS per CU.
 #pragma once
 
+#include <vector>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -173,8 +175,13 @@ hipError_t launch_solve_batch(const BatchItem *items_dev, int32_t m, int32_t *he
 int device_cus();
 hipError_t launch_service(ServiceCtl *ctl, const ServiceJob *ring, int32_t ring_size, int64_t *done,
                           ServiceDev *dev, int64_t idle_ticks, int workers, hipStream_t st);
-// tune.hip: values chosen by the autotuner for this process
-int64_t tuned_search_ratio(int32_t k);
+// tune.hip: values chosen by the autotuner for this process (or loaded from
+// a tuning cache), looked up by the k bucket (bit length of k) and the n
+// bucket (decimal digits of n minus one)
+int64_t tuned_search_ratio(int32_t k, int64_t n);
+int tune_bucket_k(int32_t k);
+int tune_bucket_n(int64_t n);
+void tune_cache_autoload();
 // scan.hip: whole-matrix best-transfer table.  A tile configuration: VEC
 // columns per load, LPR lanes per row, NP column groups per lane, MULT
 // resident waves of workgroups.
@@ -185,6 +192,13 @@ bool scan_cfg_valid(int32_t k, const ScanCfg &c);
 ScanCfg scan_default_cfg(int32_t k, bool vec4);
 int scan_candidates(int32_t k, bool vec4, ScanCfg *out, int max);
 void scan_set_tuned(int32_t k, bool vec4, const ScanCfg &c);
+struct ScanTuned {
+  int32_t k;
+  bool vec4;
+  ScanCfg cfg;
+};
+std::vector<ScanTuned> scan_tuned_list();
+void scan_clear_tuned();
 hipError_t launch_scan_group(int32_t k, int64_t n, const int32_t *assign, const int32_t *rank,
                              uint64_t *W, void *work, bool regroup, hipStream_t st);
 hipError_t launch_scan_only(int32_t k, const int32_t *cm, void *work, const ScanCfg &c,

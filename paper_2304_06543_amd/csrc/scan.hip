@@ -348,6 +348,18 @@ void scan_set_tuned(int32_t k, bool vec4, const ScanCfg &c) {
   g_tuned[tuned_key(k, vec4)] = c;
 }
 
+std::vector<ScanTuned> scan_tuned_list() {
+  std::lock_guard<std::mutex> g(g_tuned_mu);
+  std::vector<ScanTuned> out;
+  for (const auto &kv : g_tuned) out.push_back(ScanTuned{(int32_t)(kv.first / 2), (kv.first & 1) != 0, kv.second});
+  return out;
+}
+
+void scan_clear_tuned() {
+  std::lock_guard<std::mutex> g(g_tuned_mu);
+  g_tuned.clear();
+}
+
 namespace {
 __global__ void differ_kernel(const uint64_t *__restrict__ a, const uint64_t *__restrict__ b,
                               int64_t count, int32_t *flag) {
@@ -413,6 +425,7 @@ hipError_t launch_full_scan(int32_t k, int64_t n, const int32_t *cm, const int32
   if (e != hipSuccess || n == 0) return e;
   const bool vec4 = scan_vec4_ok(k, cm);
   ScanCfg c = scan_default_cfg(k, vec4);
+  tune_cache_autoload();
   {
     std::lock_guard<std::mutex> g(g_tuned_mu);
     auto it = g_tuned.find(tuned_key(k, vec4));

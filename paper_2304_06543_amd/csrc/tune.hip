@@ -23,8 +23,16 @@
 // tuned choice is a matter of time only.
 #include <hip/hip_runtime.h>
 
+#include <cctype>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/lbdd.h"
 #include "instance.hpp"
@@ -33,13 +41,40 @@
 namespace lbdd {
 namespace {
 std::mutex g_mu;
-std::map<int32_t, int64_t> g_ratio;   // k -> tuned search ratio (x16)
+std::map<std::pair<int, int>, int64_t> g_ratio;   // (k bucket, n bucket) -> search ratio (x16)
+std::once_flag g_autoload;
 }  // namespace
 
-int64_t tuned_search_ratio(int32_t k) {
+int tune_bucket_k(int32_t k) {
+  int b = 0;
+  while (k > 0) { ++b; k >>= 1; }
+  return b;                                       // k in [2^(b-1), 2^b)
+}
+
+int tune_bucket_n(int64_t n) {
+  int b = 0;
+  while (n >= 10) { ++b; n /= 10; }
+  return b;                                       // n in [10^b, 10^(b+1))
+}
+
+int64_t tuned_search_ratio(int32_t k, int64_t n) {
+  tune_cache_autoload();
   std::lock_guard<std::mutex> g(g_mu);
-  auto it = g_ratio.find(k);
+  auto it = g_ratio.find({tune_bucket_k(k), tune_bucket_n(n)});
   return it == g_ratio.end() ? DEFAULT_SEARCH_RATIO : it->second;
+}
+
+// The tuning cache named by LBDD_TUNE_CACHE, read once per process on the
+// first lookup (for this device's architecture); a missing or unreadable
+// file leaves the defaults, and the caller's last error is kept.
+void tune_cache_autoload() {
+  std::call_once(g_autoload, [] {
+    const char *path = std::getenv("LBDD_TUNE_CACHE");
+    if (!path || !*path) return;
+    const std::string saved = g_err;
+    (void)lbdd_tune_load(path, nullptr);
+    g_err = saved;
+  });
 }
 }  // namespace lbdd
 
@@ -114,7 +149,7 @@ int lbdd_tune_search(int32_t k, int64_t n, const int32_t *cm, const int32_t *cap
     if (times[c] < NOISE * base && times[c] < times[best]) best = c;
   {
     std::lock_guard<std::mutex> g(lbdd::g_mu);
-    lbdd::g_ratio[k] = CAND[best];
+    lbdd::g_ratio[{lbdd::tune_bucket_k(k), lbdd::tune_bucket_n(n)}] = CAND[best];
   }
   *ratio_out = CAND[best];
   return NC;
@@ -197,6 +232,246 @@ int lbdd_tune_best_transfers(int32_t k, int64_t n, const int32_t *cm, const int3
   if (e == hipSuccess) e = lbdd::launch_scan_only(k, cm, work, cand[best], W, st);
   if (e != hipSuccess) return hip_err(e, "scan");
   return nc;
+}
+
+
+// ---- tuning cache ---------------------------------------------------------
+// JSON: {"format": "lbdd-tune-1", "entries": [ {"arch": .., "kind": "search",
+// "k_bucket": .., "n_bucket": .., "ratio": ..} | {"arch": .., "kind": "scan",
+// "k": .., "vec4": 0|1, "config": [vec, lpr, np, mult]} ... ]}
+
+}  // extern "C"
+
+namespace {
+
+// the part of the current device's architecture name before any feature
+// suffix (gfx950:sramecc+:xnack- -> gfx950)
+bool device_arch(std::string *out) {
+  int dev = 0;
+  hipDeviceProp_t p;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return false;
+  std::string a = p.gcnArchName;
+  const size_t c = a.find(':');
+  *out = c == std::string::npos ? a : a.substr(0, c);
+  return !out->empty();
+}
+
+// A small JSON reader for the cache's own format: objects, arrays, strings
+// without escapes other than \" and \\, numbers, true, false, null.
+struct JVal {
+  enum Kind { NUL, BOOL, NUM, STR, ARR, OBJ } kind = NUL;
+  double num = 0;
+  std::string str;
+  std::vector<JVal> arr;
+  std::vector<std::pair<std::string, JVal>> obj;
+  const JVal *get(const char *key) const {
+    for (const auto &kv : obj)
+      if (kv.first == key) return &kv.second;
+    return nullptr;
+  }
+};
+
+struct JParser {
+  const char *p, *end;
+  int depth = 0;
+  void ws() { while (p < end && (*p == ' ' || *p == '\t' || *p == '\n' || *p == '\r')) ++p; }
+  bool lit(const char *w) {
+    const size_t m = strlen(w);
+    if ((size_t)(end - p) < m || strncmp(p, w, m) != 0) return false;
+    p += m;
+    return true;
+  }
+  bool string(std::string *out) {
+    if (p >= end || *p != '"') return false;
+    ++p;
+    out->clear();
+    while (p < end && *p != '"') {
+      if (*p == '\\') {
+        if (p + 1 >= end || (p[1] != '"' && p[1] != '\\')) return false;
+        ++p;
+      }
+      out->push_back(*p++);
+    }
+    if (p >= end) return false;
+    ++p;
+    return true;
+  }
+  bool value(JVal *v) {
+    if (++depth > 16) return false;
+    ws();
+    if (p >= end) return false;
+    bool ok = true;
+    if (*p == '{') {
+      v->kind = JVal::OBJ;
+      ++p;
+      ws();
+      if (p < end && *p == '}') { ++p; --depth; return true; }
+      for (;;) {
+        std::string key;
+        JVal x;
+        ws();
+        if (!string(&key)) return false;
+        ws();
+        if (p >= end || *p++ != ':') return false;
+        if (!value(&x)) return false;
+        v->obj.emplace_back(key, std::move(x));
+        ws();
+        if (p < end && *p == ',') { ++p; continue; }
+        if (p < end && *p == '}') { ++p; break; }
+        return false;
+      }
+    } else if (*p == '[') {
+      v->kind = JVal::ARR;
+      ++p;
+      ws();
+      if (p < end && *p == ']') { ++p; --depth; return true; }
+      for (;;) {
+        JVal x;
+        if (!value(&x)) return false;
+        v->arr.push_back(std::move(x));
+        ws();
+        if (p < end && *p == ',') { ++p; continue; }
+        if (p < end && *p == ']') { ++p; break; }
+        return false;
+      }
+    } else if (*p == '"') {
+      v->kind = JVal::STR;
+      ok = string(&v->str);
+    } else if (lit("true")) {
+      v->kind = JVal::BOOL; v->num = 1;
+    } else if (lit("false")) {
+      v->kind = JVal::BOOL; v->num = 0;
+    } else if (lit("null")) {
+      v->kind = JVal::NUL;
+    } else {
+      char buf[64];
+      size_t m = 0;
+      while (p < end && m < sizeof buf - 1 && (isdigit((unsigned char)*p) || (*p && strchr("+-.eE", *p))))
+        buf[m++] = *p++;
+      buf[m] = 0;
+      char *e = nullptr;
+      v->kind = JVal::NUM;
+      v->num = strtod(buf, &e);
+      ok = m > 0 && e == buf + m && std::isfinite(v->num);
+    }
+    --depth;
+    return ok;
+  }
+};
+
+// an integer-valued number in [lo, hi]
+bool jint(const JVal *v, int64_t lo, int64_t hi, int64_t *out) {
+  if (!v || v->kind != JVal::NUM || v->num != std::floor(v->num) || v->num < (double)lo || v->num > (double)hi)
+    return false;
+  *out = (int64_t)v->num;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbdd_tune_save(const char *path, const char *arch) {
+  lbdd::g_err.clear();
+  if (!path) return fail(LBDD_E_INVAL, "path is NULL");
+  std::string a;
+  if (arch) a = arch;
+  else if (!device_arch(&a)) return fail(LBDD_E_DEVICE, "cannot read the device architecture");
+  if (a.empty() || a.find_first_of("\\\"") != std::string::npos) return fail(LBDD_E_INVAL, "bad arch name");
+  std::vector<std::pair<std::pair<int, int>, int64_t>> search;
+  {
+    std::lock_guard<std::mutex> g(lbdd::g_mu);
+    for (const auto &kv : lbdd::g_ratio) search.push_back(kv);
+  }
+  const std::vector<lbdd::ScanTuned> scan = lbdd::scan_tuned_list();
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE *f = fopen(tmp.c_str(), "w");
+  if (!f) return fail(LBDD_E_INVAL, "cannot write %s", tmp.c_str());
+  fprintf(f, "{\"format\": \"lbdd-tune-1\", \"entries\": [");
+  bool first = true;
+  for (const auto &e : search) {
+    fprintf(f, "%s\n  {\"arch\": \"%s\", \"kind\": \"search\", \"k_bucket\": %d, \"n_bucket\": %d, \"ratio\": %lld}",
+            first ? "" : ",", a.c_str(), e.first.first, e.first.second, (long long)e.second);
+    first = false;
+  }
+  for (const auto &e : scan) {
+    fprintf(f, "%s\n  {\"arch\": \"%s\", \"kind\": \"scan\", \"k\": %d, \"vec4\": %d, \"config\": [%d, %d, %d, %d]}",
+            first ? "" : ",", a.c_str(), e.k, e.vec4 ? 1 : 0, e.cfg.vec, e.cfg.lpr, e.cfg.np, e.cfg.mult);
+    first = false;
+  }
+  fprintf(f, "\n]}\n");
+  const bool ok = fflush(f) == 0 && !ferror(f);
+  if (fclose(f) != 0 || !ok || rename(tmp.c_str(), path) != 0) {
+    (void)remove(tmp.c_str());
+    return fail(LBDD_E_INVAL, "cannot write %s", path);
+  }
+  return (int)(search.size() + scan.size());
+}
+
+int lbdd_tune_load(const char *path, const char *arch) {
+  lbdd::g_err.clear();
+  if (!path) return fail(LBDD_E_INVAL, "path is NULL");
+  std::string a;
+  if (arch) a = arch;
+  else if (!device_arch(&a)) return fail(LBDD_E_DEVICE, "cannot read the device architecture");
+  FILE *f = fopen(path, "rb");
+  if (!f) return fail(LBDD_E_INVAL, "cannot read %s", path);
+  std::string text;
+  char buf[4096];
+  size_t m;
+  while ((m = fread(buf, 1, sizeof buf, f)) > 0 && text.size() < (16u << 20)) text.append(buf, m);
+  fclose(f);
+  JVal root;
+  JParser ps{text.data(), text.data() + text.size()};
+  if (!ps.value(&root)) return fail(LBDD_E_INVAL, "%s is not JSON", path);
+  ps.ws();
+  if (ps.p != ps.end || root.kind != JVal::OBJ) return fail(LBDD_E_INVAL, "%s is not a tuning cache", path);
+  const JVal *fmt = root.get("format"), *ents = root.get("entries");
+  if (!fmt || fmt->kind != JVal::STR || fmt->str != "lbdd-tune-1" || !ents || ents->kind != JVal::ARR)
+    return fail(LBDD_E_INVAL, "%s is not a tuning cache (format lbdd-tune-1)", path);
+  // every entry is checked before any is applied
+  std::vector<std::pair<std::pair<int, int>, int64_t>> search;
+  std::vector<lbdd::ScanTuned> scan;
+  for (size_t i = 0; i < ents->arr.size(); ++i) {
+    const JVal &e = ents->arr[i];
+    const JVal *ea = e.get("arch"), *kind = e.get("kind");
+    if (e.kind != JVal::OBJ || !ea || ea->kind != JVal::STR || !kind || kind->kind != JVal::STR)
+      return fail(LBDD_E_INVAL, "entry %zu: arch and kind needed", i);
+    if (ea->str != a) continue;                  // tuned on another architecture
+    if (kind->str == "search") {
+      int64_t kb, nb, r;
+      if (!jint(e.get("k_bucket"), 1, 12, &kb) || !jint(e.get("n_bucket"), 0, 10, &nb) ||
+          !jint(e.get("ratio"), lbdd::SEARCH_RATIO_AUTO, lbdd::MAX_SEARCH_RATIO, &r))
+        return fail(LBDD_E_INVAL, "entry %zu: bad search entry", i);
+      search.push_back({{(int)kb, (int)nb}, r});
+    } else if (kind->str == "scan") {
+      int64_t k, v4, c[4];
+      const JVal *cfg = e.get("config");
+      bool ok = jint(e.get("k"), 1, LBDD_MAX_K, &k) && jint(e.get("vec4"), 0, 1, &v4) && cfg &&
+                cfg->kind == JVal::ARR && cfg->arr.size() == 4;
+      for (int j = 0; ok && j < 4; ++j) ok = jint(&cfg->arr[j], 1, 64, &c[j]);
+      const lbdd::ScanCfg sc{(int32_t)c[0], (int32_t)c[1], (int32_t)c[2], (int32_t)c[3]};
+      if (!ok || sc.vec != (v4 ? 4 : 1) || !lbdd::scan_cfg_valid((int32_t)k, sc))
+        return fail(LBDD_E_INVAL, "entry %zu: bad scan entry", i);
+      scan.push_back(lbdd::ScanTuned{(int32_t)k, v4 != 0, sc});
+    } else {
+      return fail(LBDD_E_INVAL, "entry %zu: unknown kind", i);
+    }
+  }
+  {
+    std::lock_guard<std::mutex> g(lbdd::g_mu);
+    for (const auto &e : search) lbdd::g_ratio[e.first] = e.second;
+  }
+  for (const auto &e : scan) lbdd::scan_set_tuned(e.k, e.vec4, e.cfg);
+  return (int)(search.size() + scan.size());
+}
+
+void lbdd_tune_clear(void) {
+  {
+    std::lock_guard<std::mutex> g(lbdd::g_mu);
+    lbdd::g_ratio.clear();
+  }
+  lbdd::scan_clear_tuned();
 }
 
 }  // extern "C"

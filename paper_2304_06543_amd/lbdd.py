@@ -46,7 +46,7 @@ EXPORTS = ("lbdd_create", "lbdd_solve", "lbdd_solve_iters", "lbdd_solve_batch", 
            "lbdd_create_penalty_table", "lbdd_road_cm_work_bytes", "lbdd_road_cost_matrix",
            "lbdd_best_transfers_batch_work_bytes", "lbdd_best_transfers_batch",
            "lbdd_best_transfers_noalloc", "lbdd_read_ceiling", "lbdd_server_cancel",
-           "lbdd_server_set_queue_timeout")
+           "lbdd_server_set_queue_timeout", "lbdd_tune_save", "lbdd_tune_load", "lbdd_tune_clear")
 JOB_QUEUED, JOB_RUNNING, JOB_DONE = 0, 1, 2
 SERVER_STATS = ("submitted", "admitted", "finished", "failed", "kernel_launches",
                 "peak_jobs", "peak_bytes", "bytes_now", "workers", "cancelled", "timed_out")
@@ -91,6 +91,9 @@ def load(path: str = LIB_PATH):
         "lbdd_server_stats": ([P, P, I32], C.c_int),
         "lbdd_server_destroy": ([P], None),
         "lbdd_server_cancel": ([P, C.c_uint64], C.c_int),
+        "lbdd_tune_save": ([C.c_char_p, C.c_char_p], C.c_int),
+        "lbdd_tune_load": ([C.c_char_p, C.c_char_p], C.c_int),
+        "lbdd_tune_clear": ([], None),
         "lbdd_server_set_queue_timeout": ([P, C.c_double], C.c_int),
         "lbdd_set_option": ([P, I32, I64], C.c_int),
         "lbdd_get_option": ([P, I32, C.POINTER(I64)], C.c_int),
@@ -433,6 +436,23 @@ def tune_search(cm, capacity, penalty, iters: int, stream=None):
                                        C.cast(ms, C.c_void_p), 8))
     del keep
     return ratio.value, [float(ms[i]) for i in range(m)]
+
+
+def tune_save(path: str, arch: str = None) -> int:
+    """lbdd_tune_save: write this process's tuned choices to a JSON tuning
+    cache, tagged with arch (None: the current device's)."""
+    return _check(load().lbdd_tune_save(os.fsencode(path), arch.encode() if arch else None))
+
+
+def tune_load(path: str, arch: str = None) -> int:
+    """lbdd_tune_load: apply the cache's entries tuned on arch (None: the
+    current device's); returns how many were applied."""
+    return _check(load().lbdd_tune_load(os.fsencode(path), arch.encode() if arch else None))
+
+
+def tune_clear():
+    """lbdd_tune_clear: forget every tuned choice of this process."""
+    load().lbdd_tune_clear()
 
 
 def tune_best_transfers(cm, assign, rank, reps: int = 5, W=None, work=None, stream=None):
