@@ -107,3 +107,17 @@ def test_missing_file_and_null_path(lib, tmp_path):
         lib.tune_load(str(tmp_path / "none.json"), "gfx950")
     with pytest.raises(lbdd.LbddError):
         lib.tune_save(str(tmp_path / "no_dir" / "x.json"), "gfx950")
+
+
+def test_json_reader_under_sanitizers(tmp_path):
+    """The cache's JSON reader, built on its own with the address and
+    undefined-behaviour sanitizers: values, refusals, and random damage."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    exe = str(tmp_path / "tune_cache_check")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=all", "-o", exe,
+                    os.path.join(root, "tests", "tune_cache_check.cpp")], check=True)
+    p = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert p.returncode == 0, p.stdout + p.stderr
+    assert "ok" in p.stdout
