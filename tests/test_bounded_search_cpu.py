@@ -371,3 +371,134 @@ def test_one_wide_window_relaxes_centers_again():
             windowed_rounds(W, s, pot, mode, load, cap, pen, 10 ** 12, counts)
             again += max(counts) > 1
     assert again > 30
+
+
+def windowed_threads(W, s, pot, mode, load, cap, pen, width, T, G, rng):
+    """The kernel's windowed loop at the level of its threads: T threads for
+    the pass over the pending flags, G threads per target for the
+    relaxations (frontier entries g, g + G, ...), the counters of a round in
+    one of three rotating slots (slot c + 1 cleared by thread 0 at the start
+    of round c), labels packed as the kernel packs them, and between two
+    barriers every thread's steps interleaved at random.  Each thread takes
+    the window decision of a round after that round's second barrier, while
+    faster threads already run the next round's pass (no barrier between
+    them).  Returns the labels below the bound; asserts that every thread
+    takes the same decisions."""
+    k = W.shape[0]
+
+    def in_weight(u):
+        if mode == 0:
+            return None if W[u, s] == pins.KEY_NONE else _delta(W[u, s])
+        return (int(pen[u]) if load[u] >= cap[u] else 0) - int(pen[s])
+
+    if mode == 0:
+        Db = 0
+    else:
+        others = [int(pot[u]) + in_weight(u) - int(pot[s]) for u in range(k) if u != s]
+        Db = -min(others) if others else -(1 << 46)
+    NONE = (1 << 64) - 1
+    LB = 1 << 41
+    pack = lambda d, e, p: ((d + LB) << 22) | (e << 11) | p
+    dist = lambda l: (l >> 22) - LB
+    lab = [NONE] * k
+    lab[s] = pack(0, 0, 0)
+    pend = [v == s for v in range(k)]
+    r = lambda l, v: dist(l) + int(pot[s]) - int(pot[v])
+    wkey = lambda l, v: ((r(l, v) + (1 << 46)) << 11) | ((l >> 11) & 0x7FF)
+    key_db = (Db + (1 << 46)) << 11
+    nfront = [0, 0, 0]
+    wlo = [NONE, NONE, NONE]
+    front = []                                  # (center, base) taken in the round
+    hi0 = wkey(lab[s], s) + 1
+    st = [dict(hi=hi0, win=0, done=False) for _ in range(T)]
+    log = [[] for _ in range(T)]                # each thread's decisions
+
+    def run_interleaved(progs):
+        live = list(progs)
+        while live:
+            i = int(rng.integers(len(live)))
+            try:
+                next(live[i])
+            except StopIteration:
+                live.pop(i)
+
+    prev = None                                 # slot of the round whose decision is pending
+    for it in range(4 * k + 16):
+        c = it % 3
+
+        def step(t):
+            h = st[t]
+            if prev is not None:                # the previous round's window decision
+                lo = wlo[prev]
+                yield
+                if lo >= h["hi"] or h["win"] == 0:
+                    if lo == NONE or lo >= key_db:
+                        h["done"] = True
+                    else:
+                        h["hi"] = lo + width
+                        h["win"] += 1
+                log[t].append((h["hi"], h["win"], h["done"]))
+                if h["done"]:
+                    return
+            if t == 0:
+                nfront[(c + 1) % 3] = 0
+                wlo[(c + 1) % 3] = NONE
+                yield
+            for v in range(t, k, T):
+                if pend[v]:
+                    l = lab[v]
+                    key = wkey(l, v)
+                    yield
+                    if key < h["hi"]:
+                        pend[v] = False
+                        front.append((v, (l & ~0x7FF) + (1 << 11) + v))
+                        nfront[c] += 1
+                    else:
+                        wlo[c] = min(wlo[c], key)
+                    yield
+        run_interleaved([step(t) for t in range(T)])
+        assert all(x == log[0] for x in log)
+        if st[0]["done"]:
+            break
+        nf = nfront[c]                          # barrier: every thread reads it
+        if nf == 0:
+            break
+        assert nf == len(front)
+        entries = list(front)
+        front.clear()
+
+        def relax(v, g):
+            best = NONE
+            for (u, base) in entries[g::G]:
+                if W[u, v] != pins.KEY_NONE:
+                    best = min(best, base + (_delta(W[u, v]) << 22))
+                yield
+            old = lab[v]                        # atomic minimum, old value returned
+            lab[v] = min(old, best)
+            if best < old and r(best, v) < Db:
+                pend[v] = True
+                wlo[c] = min(wlo[c], wkey(best, v))
+            yield
+        run_interleaved([relax(v, g) for v in range(k) if v != s for g in range(G)])
+        prev = c                                # barrier; the decision runs in the next pass
+    rel = [v for v in range(k) if lab[v] != NONE and (v == s or r(lab[v], v) < Db)]
+    return {v: (dist(lab[v]), (lab[v] >> 11) & 0x7FF, (lab[v] & 0x7FF) if v != s else -1) for v in rel}
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("seed", range(40))
+def test_windowed_threads_match_the_pruned_labels(seed, mode):
+    """The windowed loop as its threads run it (rotating counter slots,
+    interleaved steps, one barrier between a round's pass and its
+    relaxations and one after) reaches the labels of pruned rounds, and every
+    thread takes the same window decisions."""
+    rng, k, pot, W, s, load, cap, pen = _case(seed, mode)
+    dist, pred, _ = oracle.refine_search(W, s, mode, load, cap, pen)
+    _, _, labels_p, _ = pruned_rounds(W, s, pot, mode, load, cap, pen)
+    for width in (1, 2 ** 11, 10 ** 12):
+        for T, G in ((1, 1), (3, 2), (8, 3)):
+            labs = windowed_threads(W, s, pot, mode, load, cap, pen, width, T, G, rng)
+            assert set(labs) == set(labels_p), (seed, mode, width, T)
+            for v, (d, e, p) in labs.items():
+                if v != s:
+                    assert d == dist[v] and p == pred[v], (seed, mode, width, T, v)
