@@ -597,7 +597,7 @@ def main():
                     help="instances of the batched workload scanned together by the batched scan (0: skip)")
     ap.add_argument("--batch", type=int, default=256,
                     help="instances of the batched workload solved in one launch (0: skip)")
-    ap.add_argument("--batch-plain", type=int, default=96,
+    ap.add_argument("--batch-plain", type=int, default=64,
                     help="of those, how many (the first) are also solved plainly one after another")
     ap.add_argument("--batch-cpu", type=int, default=16,
                     help="instances (least n*k) in the instance-parallel oracle sample")
