@@ -20,12 +20,16 @@
 //             not holding every unit of its center is refilled by a column
 //             scan of the center's members in the cost matrix.
 //
-// Bellman-Ford runs in synchronous rounds.  Only nodes whose label changed in
-// the previous round are relaxed from: a node that did not change cannot give
-// a strictly better label (every target already saw its value one round
-// earlier), so labels and predecessors equal those of full rounds.  Candidate
-// (label, node) pairs are packed so that one unsigned min keeps the smallest
-// label and, on ties, the smallest predecessor node.
+// The searches give the labels of synchronous Bellman-Ford rounds (shortest
+// distance, then fewest edges, then smallest predecessor), packed so that one
+// unsigned minimum orders them; that least fixpoint does not depend on the
+// order of relaxations.  They run as frontier rounds, as rounds pruned by
+// node potentials kept feasible across searches (repaired where moves break
+// them), as windowed rounds in the order of (reduced distance, edges), or in
+// Dijkstra order bounded to the centers that can still lower s_in; a
+// measured cost model picks between rounds and Dijkstra order.  Path
+// searches run on sink potentials (the cost of placing one more unit from
+// each center).
 //
 // Strict-LBDD (Appendix B, Algorithm 4) runs the same loop: the unit goes to
 // the cheapest center that still has free capacity, only Negative Cycle
@@ -34,7 +38,7 @@
 // without knowing of them; applying a dummy transfer moves no unit.
 //
 // One workgroup of 1024 threads owns the instance.  W lives in LDS when it
-// fits (k <= ~135) and in global memory (L2-resident) otherwise.
+// fits (k <= 135) and in global memory (L2-resident) otherwise.
 #include "lbdd_dev.hpp"
 
 namespace lbdd {
