@@ -589,7 +589,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip every oracle timing")
     ap.add_argument("--c3", choices=("whole", "prefix", "skip"), default="whole",
                     help="k=500, n=1,000,000: one whole solve, or its first 300,000 iterations")
-    ap.add_argument("--c3-cpu-iters", type=int, default=2000,
+    ap.add_argument("--c3-cpu-iters", type=int, default=5000,
                     help="iterations of the k=500 instance in the bounded oracle sample")
     ap.add_argument("--no-scan", action="store_true")
     ap.add_argument("--scan-reps", type=int, default=10)
