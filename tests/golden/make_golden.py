@@ -30,9 +30,10 @@ STAT_NAMES = ["cycles", "paths", "moves", "cycle_searches", "path_searches",
 
 # instances of the batched workload (index into batch_specs()) and of the
 # serving trace (index into serving_trace()) whose results are stored: k from
-# 35 to 316, n up to 4.1e5, and k > 136 (a table too large to stay in LDS)
-BATCH_IDS = (7, 0, 3, 17)
-SERVE_IDS = (2, 9, 14, 37)
+# 35 to 462, n up to 5.3e5, several with k > 135 (a table too large to stay
+# in LDS), and the largest request among the first 40 of the trace (28)
+BATCH_IDS = (7, 0, 3, 17, 28)
+SERVE_IDS = (2, 9, 14, 37, 28, 32)
 C3_PREFIX = 300_000
 
 
