@@ -30,10 +30,11 @@ STAT_NAMES = ["cycles", "paths", "moves", "cycle_searches", "path_searches",
 
 # instances of the batched workload (index into batch_specs()) and of the
 # serving trace (index into serving_trace()) whose results are stored: k from
-# 35 to 462, n up to 5.3e5, several with k > 135 (a table too large to stay
-# in LDS), and the largest request among the first 40 of the trace (28)
-BATCH_IDS = (7, 0, 3, 17, 28)
-SERVE_IDS = (2, 9, 14, 37, 28, 32)
+# 8 to 462, n up to 5.3e5, the largest k whose table stays in LDS (135) and
+# the smallest beyond it (136), several more with the table in global memory,
+# and the largest request among the first 40 of the trace (28)
+BATCH_IDS = (7, 0, 3, 17, 28, 49, 53, 233)
+SERVE_IDS = (2, 9, 14, 37, 28, 32, 29, 36)
 C3_PREFIX = 300_000
 
 
